@@ -1,0 +1,156 @@
+/*
+ * ORACLE -- test infrastructure, not part of the product.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the labeling
+ * path computes.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * Semantics (Sec. 4.2, Eq. bool_dot and Eq. approx): with M the
+ * trajectory-by-cell binary matrix and P the cell-by-proposition binary
+ * matrix,
+ *     L(i, j) = OR_k  M(i, k) AND P(k, j),
+ * and pi_j belongs to the label of transition e_i iff L(i, j) is true.
+ *
+ * Encodings: input bytes follow C truthiness (nonzero = true); output bytes
+ * are exactly 0 or 1.  P is stored dense, cell-major: O[c * n_props + p]
+ * (Sec. 4.3 keeps P as a dense two-dimensional array).  M is stored in
+ * compressed sparse row form (Sec. 4.3, Eq. csr_demo) with the arrays named
+ * by their role in the worked example: row_ptr (the paper's r, running count
+ * of true entries before each row) and col_idx (the paper's c, column index
+ * of each true entry, left to right, top to bottom).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+/*
+ * Sparse Boolean matrix product (Sec. 4.3, Alg. mat_mul), read with the
+ * indices of Eq. approx: for each listed row t, for each stored entry k of
+ * that row, OR the proposition values of cell col_idx[k] into L[t][*].  The
+ * loop over propositions is innermost; OR is commutative and idempotent, so
+ * the order of the loops does not change the result.  No early exit.
+ *
+ * rows lists which rows of M to label (n_rows of them); L receives
+ * n_rows x n_props bytes, row i of L for row rows[i] of M.
+ * Returns 0, or -1 if a column index is out of range (L is then unspecified).
+ */
+typedef struct {
+    const uint64_t *row_ptr;
+    const uint32_t *col_idx;
+    uint64_t n_cells;
+    const uint8_t *O;
+    uint32_t n_props;
+    const uint64_t *rows;
+    uint64_t lo, hi;
+    uint8_t *L;
+    int bad;
+} csr_job;
+
+static void label_rows_csr(csr_job *j)
+{
+    for (uint64_t i = j->lo; i < j->hi; ++i) {
+        uint64_t t = j->rows[i];
+        uint8_t *Lt = j->L + i * j->n_props;
+        for (uint32_t p = 0; p < j->n_props; ++p) Lt[p] = 0;
+        for (uint64_t k = j->row_ptr[t]; k < j->row_ptr[t + 1]; ++k) {
+            uint64_t c = j->col_idx[k];
+            if (c >= j->n_cells) {
+                j->bad = 1;
+                return;
+            }
+            const uint8_t *Oc = j->O + c * j->n_props;
+            for (uint32_t p = 0; p < j->n_props; ++p) Lt[p] = (uint8_t)(Lt[p] | (Oc[p] != 0));
+        }
+    }
+}
+
+static void *csr_thread(void *v)
+{
+    label_rows_csr((csr_job *)v);
+    return NULL;
+}
+
+int oracle_label_csr(const uint64_t *row_ptr, const uint32_t *col_idx, uint64_t n_cells,
+                     const uint8_t *O, uint32_t n_props, const uint64_t *rows, uint64_t n_rows,
+                     uint8_t *L, int n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    if ((uint64_t)n_threads > n_rows) n_threads = n_rows ? (int)n_rows : 1;
+    csr_job *jobs = (csr_job *)calloc((size_t)n_threads, sizeof(csr_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return -2;
+    }
+    /* static split of the row list; every thread writes disjoint rows of L */
+    for (int i = 0; i < n_threads; ++i) {
+        csr_job j = {row_ptr, col_idx, n_cells, O, n_props, rows,
+                     n_rows * (uint64_t)i / (uint64_t)n_threads,
+                     n_rows * (uint64_t)(i + 1) / (uint64_t)n_threads, L, 0};
+        jobs[i] = j;
+    }
+    for (int i = 1; i < n_threads; ++i) pthread_create(&th[i], NULL, csr_thread, &jobs[i]);
+    label_rows_csr(&jobs[0]);
+    for (int i = 1; i < n_threads; ++i) pthread_join(th[i], NULL);
+    int bad = 0;
+    for (int i = 0; i < n_threads; ++i) bad |= jobs[i].bad;
+    free(jobs);
+    free(th);
+    return bad ? -1 : 0;
+}
+
+/*
+ * Eq. bool_dot written out for a dense M (n_traj x n_cells bytes, row-major):
+ * L[t][p] = OR over every cell c of (M[t][c] AND P[c][p]).  A triple loop,
+ * for small inputs.
+ */
+void oracle_label_dense(const uint8_t *M, uint64_t n_traj, uint64_t n_cells, const uint8_t *O,
+                        uint32_t n_props, uint8_t *L)
+{
+    for (uint64_t t = 0; t < n_traj; ++t)
+        for (uint32_t p = 0; p < n_props; ++p) {
+            int acc = 0;
+            for (uint64_t c = 0; c < n_cells; ++c)
+                acc = acc || (M[t * n_cells + c] != 0 && O[c * n_props + p] != 0);
+            L[t * n_props + p] = (uint8_t)acc;
+        }
+}
+
+/*
+ * z-order index of a point by descending a binary space partition
+ * (Sec. 4.1, Alg. zcurve), as read here:
+ *   - normalise each coordinate to [0, 1] over the workspace box;
+ *   - visit axes cyclically, axis 0 first, for d levels;
+ *   - at level i (1-based) the pivot of the current axis splits its current
+ *     interval; a point at or above the pivot is on the high side and adds
+ *     2^(d - i) to the index, and the pivot moves half the interval's half
+ *     width towards the point: by 0.5^(floor((i - 1) / k) + 2).
+ * Cells are half-open, so a point on a splitting plane goes to the high side.
+ * With d = k * b this equals interleaving the b-bit cell coordinates with
+ * axis 0 as the most significant bit of every k-bit group (the equivalence
+ * the section states).
+ */
+uint64_t oracle_zorder(int k, int d, const double *x, const double *lo, const double *hi)
+{
+    double z[16], piv[16];
+    for (int a = 0; a < k; ++a) {
+        z[a] = (x[a] - lo[a]) / (hi[a] - lo[a]);
+        piv[a] = 0.5;
+    }
+    uint64_t n = 0;
+    int j = 0;
+    for (int i = 1; i <= d; ++i) {
+        double step = pow(0.5, (double)((i - 1) / k + 2));
+        if (z[j] >= piv[j]) {
+            n += (uint64_t)1 << (d - i);
+            piv[j] += step;
+        } else {
+            piv[j] -= step;
+        }
+        j = (j + 1) % k;
+    }
+    return n;
+}
