@@ -1,0 +1,266 @@
+/*
+ * lbl.h -- C ABI of the MI355X labeling library.
+ *
+ * The library constructs the labeling function of a fixed discrete
+ * abstraction from one perception frame (Sec. 4).  Following the reduction of
+ * Sec. 4.2 (Eq. bool_dot, Eq. approx), the labels are the Boolean matrix
+ * product
+ *
+ *     L[t][p] = OR_c  T[t][c] AND O[c][p]
+ *
+ * where T (the paper's M) is the trajectory-by-cell swept-set matrix: row t is
+ * the binary vector of the grid cells swept by trajectory t (Sec. 4.1), and O
+ * (the paper's P) is the cell-by-proposition matrix of one frame: column p is
+ * the binary vector of the cells that proposition p's region intersects.
+ * L[t][p] = 1 means proposition p belongs to the label of transition t
+ * (Sec. 3, Eq. 3 and Sec. 4, Eq. labeling_op on the grid).
+ *
+ * T is precomputed once and stays resident in device memory (the abstraction
+ * is fixed and reused across planning queries by equivariance, Sec. 1 and
+ * Sec. 5); each query sends only O.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an lbl_status; nothing throws across the ABI.
+ *     On a non-OK status, lbl_last_error() returns a message for the calling
+ *     thread, output buffers are unspecified, and no handle is leaked.
+ *   - Cells are identified by row-major ids c = iy * nx + ix on the caller's
+ *     side.  The library stores cells in its own device order internally; the
+ *     result does not depend on it.
+ *   - Input bytes follow C truthiness (nonzero = true).  Output bytes are
+ *     exactly 0 or 1.
+ *   - All sizes are element counts unless stated otherwise.
+ *   - hip_stream arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Device work is stream-ordered: with device pointers a
+ *     call returns once its work is enqueued, and the caller's buffers must
+ *     stay valid until the stream reaches it.
+ */
+#ifndef LBL_H
+#define LBL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBL_OK = 0,
+    LBL_EINVAL = 1,    /* invalid argument (null pointer, size, range, mismatch) */
+    LBL_ENOMEM = 2,    /* device allocation or memory budget failure */
+    LBL_EDEVICE = 3,   /* a HIP runtime error; the message names the call */
+    LBL_EBUSY = 4,     /* the server's request queue is full */
+    LBL_ETIMEDOUT = 5, /* lbl_serve_wait timed out; the request is still pending */
+    LBL_ECLOSED = 6    /* the server is stopping or stopped */
+} lbl_status;
+
+typedef struct lbl_abs *lbl_abs_t;       /* owns the device-resident T */
+typedef struct lbl_server *lbl_server_t; /* a serving loop */
+
+/* Occupancy grid over the rectangular workspace (Sec. 4.1).  nx and ny are
+ * cell counts per axis and must be positive multiples of 8; cell_m is the
+ * cell side in metres (informational). */
+typedef struct {
+    uint32_t nx, ny;
+    float cell_m;
+    uint32_t reserved; /* must be 0 */
+} lbl_grid;
+
+/* ---- flags for lbl_load_abstraction* ---------------------------------- */
+#define LBL_LOAD_KEEP_INT8 0x1u    /* also keep an int8 copy of T (N_t x N_c bytes) */
+#define LBL_LOAD_INPUT_DEVICE 0x2u /* the input arrays are device pointers */
+
+/* ---- flags for lbl_label_frame / lbl_label_batch ---------------------- */
+#define LBL_HOST_PTRS 0x1u      /* O and L are host pointers; the call is synchronous */
+#define LBL_KERNEL_AUTO 0x00u   /* kernel and tile chosen by the autotuner cache */
+#define LBL_KERNEL_BITS 0x10u   /* bitpacked AND/OR wavefront kernel */
+#define LBL_KERNEL_MFMA 0x20u   /* int8 MFMA kernel, T expanded from its bitpacked copy */
+#define LBL_KERNEL_MFMA_I8 0x40u /* int8 MFMA kernel reading the int8 copy of T
+                                   (needs LBL_LOAD_KEEP_INT8) */
+#define LBL_KERNEL_MASK 0xF0u
+
+/*
+ * Load T given in compressed sparse row form (Sec. 4.3, Eq. csr_demo):
+ * row_ptr[t] is the number of true entries in rows 0..t-1 (n_traj + 1
+ * values, row_ptr[0] == 0, non-decreasing) and col_idx[row_ptr[t] ..
+ * row_ptr[t+1]) are the row-major cell ids of row t's true entries.  Column
+ * ids may be unsorted or repeated within a row (OR is idempotent).
+ *
+ * The arrays are host pointers unless LBL_LOAD_INPUT_DEVICE is set.  They are
+ * copied; the caller may free them when the call returns.  The returned
+ * handle owns the device copy until lbl_free_abstraction.  The call is
+ * synchronous and uses the current HIP device.
+ *
+ * Errors: LBL_EINVAL for a null pointer, n_traj == 0, nx or ny not a positive
+ * multiple of 8, reserved != 0, row_ptr[0] != 0 or decreasing, or a column id
+ * >= nx * ny; LBL_ENOMEM if device memory runs out; LBL_EDEVICE on a HIP
+ * error.
+ */
+lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uint64_t *row_ptr,
+                                const uint32_t *col_idx, uint32_t flags, lbl_abs_t *out);
+
+/*
+ * Load T given dense: n_traj x (nx * ny) bytes, row-major, cell ids
+ * row-major (nonzero = cell swept).  Otherwise as lbl_load_abstraction.
+ */
+lbl_status lbl_load_abstraction_dense(const lbl_grid *grid, uint64_t n_traj, const uint8_t *T,
+                                      uint32_t flags, lbl_abs_t *out);
+
+/* Release an abstraction.  The caller must ensure no enqueued work still
+ * uses it.  A NULL handle is accepted and ignored. */
+lbl_status lbl_free_abstraction(lbl_abs_t a);
+
+/* Sizes of a loaded abstraction. */
+typedef struct {
+    uint64_t n_traj;
+    uint32_t nx, ny;
+    uint32_t n_words;        /* 64-cell words per row (nx * ny / 64) */
+    uint32_t row_stride;     /* words between consecutive rows of the bitpacked T */
+    uint64_t bits_bytes;     /* device bytes of the bitpacked T */
+    uint64_t int8_bytes;     /* device bytes of the int8 T (0 if not kept) */
+    uint64_t nonzero_words;  /* words of the bitpacked T holding at least one set cell */
+    uint64_t set_cells;      /* distinct (trajectory, cell) pairs set in T */
+} lbl_abs_info;
+
+lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);
+
+/*
+ * Label one frame (Eq. approx).
+ *   O : n_cells x n_props bytes, cell-major (O[c * n_props + p]), c row-major;
+ *   L : n_traj x n_props bytes, row-major (L[t * n_props + p]), written 0/1.
+ *   n_props in [1, 64].
+ * With LBL_HOST_PTRS, O and L are host memory and the call returns after L
+ * is written (the transfers are part of the call).  Otherwise both are
+ * device pointers and the call is asynchronous on hip_stream.  Distinct
+ * streams may label the same abstraction concurrently.
+ *
+ * The first call on a stream (or one needing a larger workspace) allocates
+ * and synchronizes that stream; later calls do not.
+ *
+ * Errors: LBL_EINVAL for a null handle or pointer, n_props outside [1, 64],
+ * an unknown kernel flag, or LBL_KERNEL_MFMA_I8 without an int8 copy of T.
+ */
+lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint8_t *L,
+                           uint32_t flags, void *hip_stream);
+
+/*
+ * Label many frames, possibly against different abstractions, in one
+ * persistent-kernel launch.  Each job is one frame as in lbl_label_frame.
+ * Jobs on the same abstraction share each pass over T: their propositions
+ * are concatenated (at most LBL_BATCH_MAX_PROPS per abstraction per call).
+ * The whole pipeline of a batch (O packing, labeling) is recorded once as a
+ * HIP graph keyed by the batch's shape and buffers and replayed when the same
+ * batch is submitted again.  Results are identical to labeling each job alone.
+ *
+ * Errors: as lbl_label_frame for every job, plus LBL_EINVAL for n_jobs == 0
+ * or more than LBL_BATCH_MAX_PROPS propositions on one abstraction.
+ */
+typedef struct {
+    lbl_abs_t a;
+    const uint8_t *O;
+    uint32_t n_props;
+    uint8_t *L;
+} lbl_job;
+
+#define LBL_BATCH_MAX_PROPS 1024u
+
+lbl_status lbl_label_batch(const lbl_job *jobs, size_t n_jobs, uint32_t flags, void *hip_stream);
+
+/*
+ * Autotuner.  lbl_tune times the candidate kernels and tile shapes for the
+ * abstraction's shape class (row count, word count, proposition count, T word
+ * density) on one frame and records the fastest; LBL_KERNEL_AUTO then uses
+ * it.  O_sample is a device frame (n_cells x n_props, as in lbl_label_frame)
+ * or NULL, in which case every cell of every proposition is set independently
+ * with probability density_pct / 100 (the Bernoulli subset model of Sec. 5.1,
+ * which favours early termination; pass a real frame when one is available).
+ * The call synchronizes hip_stream.  lbl_tune_save / lbl_tune_load persist the
+ * cache as JSON text.
+ */
+lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint32_t density_pct,
+                    void *hip_stream);
+lbl_status lbl_tune_save(const char *path);
+lbl_status lbl_tune_load(const char *path);
+/* Describe the choice AUTO makes for (a, n_props) into buf (NUL-terminated). */
+lbl_status lbl_tune_describe(lbl_abs_t a, uint32_t n_props, char *buf, size_t buf_len);
+
+/*
+ * Serving loop (continuous batching).  lbl_serve_start creates a server with
+ * its own streams and a worker thread.  lbl_serve_submit enqueues one frame
+ * (device pointers, as in lbl_label_frame) and returns a ticket; requests are
+ * admitted onto the GPU as memory within hbm_budget_bytes (for the server's
+ * internal per-request buffers) frees up, grouped per abstraction into
+ * batches of at most max_batch_frames, and a batch is launched while earlier
+ * ones are still running.  The library does not copy O or L: both must stay
+ * valid until lbl_serve_wait returns LBL_OK for the ticket.
+ *
+ * lbl_serve_wait blocks until the ticket completes (LBL_OK), timeout_us
+ * elapses (LBL_ETIMEDOUT; negative = wait forever), or the request failed
+ * (its error status).  Each ticket can be waited for successfully once.
+ * Latency is measured from submit to completion on the host's monotonic
+ * clock.  submit, wait and stats may be called from any thread.
+ */
+typedef struct {
+    uint64_t hbm_budget_bytes; /* bytes for in-flight requests' internal buffers */
+    uint32_t max_batch_frames; /* frames per launched batch, >= 1 */
+    uint32_t max_wait_us;      /* how long a non-full batch may wait for company */
+    uint32_t max_queue;        /* pending requests before submit returns LBL_EBUSY */
+    uint32_t n_streams;        /* batches that may be in flight at once, 1..8 */
+} lbl_serve_cfg;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, failed;
+    uint64_t batches;
+    uint64_t pairs;          /* labeled (trajectory, proposition) pairs */
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double wall_s;           /* time since start */
+    double pairs_per_s;
+    uint64_t max_in_flight;  /* most requests on the GPU at once */
+    uint64_t budget_high_water;
+} lbl_serve_stats;
+
+lbl_status lbl_serve_start(const lbl_serve_cfg *cfg, lbl_server_t *out);
+lbl_status lbl_serve_submit(lbl_server_t s, lbl_abs_t a, const uint8_t *O, uint32_t n_props,
+                            uint8_t *L, uint64_t *ticket);
+lbl_status lbl_serve_wait(lbl_server_t s, uint64_t ticket, int64_t timeout_us);
+lbl_status lbl_serve_stats_get(lbl_server_t s, lbl_serve_stats *out);
+lbl_status lbl_serve_stop(lbl_server_t s);
+
+/*
+ * Kernel timing for measurement.  While enabled, lbl_label_frame and
+ * lbl_label_batch record HIP events on their stream around each kernel they
+ * launch.  lbl_profile_read waits for the recorded events and returns totals
+ * since the last lbl_profile_enable.  Disabled by default; enabling or
+ * disabling resets the totals.  Not for use under graph capture.
+ */
+typedef struct {
+    uint64_t pack_launches;   /* O packing kernels timed */
+    uint64_t label_launches;  /* labeling kernels timed */
+    double pack_ms;           /* summed durations */
+    double label_ms;
+} lbl_profile;
+
+lbl_status lbl_profile_enable(int on);
+lbl_status lbl_profile_read(lbl_profile *out);
+
+/*
+ * Device cell order.  Cells are grouped into 8 x 8 tiles, one 64-bit word per
+ * tile; words follow the z-order of the tiles (Sec. 4.1, Alg. zcurve; ranked
+ * among the grid's tiles when the tile grid is not a power-of-two square) and
+ * bits follow the z-order of the cells inside the tile, x as the more
+ * significant bit of each pair.  For a 2^k x 2^k grid, word * 64 + bit is the
+ * cell's z-order index.  Host-only; needs no device.
+ */
+lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word, uint32_t *bit);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *lbl_last_error(void);
+
+/* Library version string. */
+const char *lbl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBL_H */

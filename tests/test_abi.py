@@ -1,0 +1,99 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, computes the device cell order on the host, and rejects bad arguments
+before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_02612_amd import lbl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbl_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = lbl.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(lbl.EXPORTS) == set(names)
+
+
+def test_version_and_empty_error():
+    assert "gfx950" in lbl.version()
+
+
+@pytest.mark.parametrize("bits", [1, 3, 6])
+def test_cell_order_is_zorder_on_square_power_of_two_grids(bits):
+    # side 2^bits tiles of 8 cells: word * 64 + bit must be the cell's z-order
+    # index from the oracle's reading of the z-curve descent
+    n = 8 << bits
+    d = 2 * (bits + 3)
+    rng = np.random.default_rng(bits)
+    cells = rng.choice(n * n, size=min(n * n, 600), replace=False)
+    for c in cells:
+        ix, iy = int(c) % n, int(c) // n
+        w, b = lbl.cell_position(n, n, int(c))
+        z = oracle.zorder([ix + 0.5, iy + 0.5], [0.0, 0.0], [float(n), float(n)], d)
+        assert w * 64 + b == z
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (24, 40), (64, 16), (8, 72)])
+def test_cell_order_is_a_bijection_with_tiles_in_words(nx, ny):
+    seen = set()
+    for c in range(nx * ny):
+        w, b = lbl.cell_position(nx, ny, c)
+        assert 0 <= b < 64 and 0 <= w < nx * ny // 64
+        seen.add((w, b))
+        ix, iy = c % nx, c // nx
+        # all 64 cells of an 8x8 tile share a word
+        w0, _ = lbl.cell_position(nx, ny, (iy // 8 * 8) * nx + ix // 8 * 8)
+        assert w == w0
+    assert len(seen) == nx * ny
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    rp = np.array([0, 1], np.uint64)
+    ci = np.array([0], np.uint32)
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction(12, 8, rp, ci)
+    assert e.value.status == lbl.EINVAL and "multiples of 8" in str(e.value)
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction(8, 8, np.array([1, 2], np.uint64), ci)
+    assert e.value.status == lbl.EINVAL
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction(8, 8, np.array([0, 3, 2], np.uint64), np.zeros(3, np.uint32))
+    assert "non-decreasing" in str(e.value)
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction(8, 8, rp, ci, flags=0x100)
+    assert e.value.status == lbl.EINVAL
+    with pytest.raises(lbl.LblError):
+        lbl.label_frame(None, 1, 8, 1)
+    with pytest.raises(lbl.LblError):
+        lbl.cell_position(8, 8, 64)
+    # n_traj == 0
+    g = lbl.Grid(8, 8, 0.5, 0)
+    h = ctypes.c_void_p()
+    st = lbl.lib().lbl_load_abstraction(ctypes.byref(g), 0, rp.ctypes.data, ci.ctypes.data, 0, ctypes.byref(h))
+    assert st == lbl.EINVAL and h.value is None
+    # reserved must be zero
+    g = lbl.Grid(8, 8, 0.5, 1)
+    st = lbl.lib().lbl_load_abstraction(ctypes.byref(g), 1, rp.ctypes.data, ci.ctypes.data, 0, ctypes.byref(h))
+    assert st == lbl.EINVAL
+
+
+def test_batch_and_serve_reject_bad_arguments():
+    with pytest.raises(lbl.LblError):
+        lbl.label_batch([], 0)
+    with pytest.raises(lbl.LblError):
+        lbl.serve_start(max_batch_frames=0)

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP library's labels equal the oracle's, byte for byte.
+
+Every case prints what it runs (flushed) before touching the device.  Inputs
+come from the seeded generator; expected labels only from the oracle.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+torch = pytest.importorskip("torch")
+from paper_1810_02612_amd import lbl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = {"bits": lbl.KERNEL_BITS, "mfma": lbl.KERNEL_MFMA, "mfma_i8": lbl.KERNEL_MFMA_I8}
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def expect(a, O, rows=None):
+    return oracle.label_csr(a.row_ptr, a.col_idx, a.grid.n_cells, O, rows=rows, threads=THREADS)
+
+
+def load(a, flags=0):
+    return lbl.load_abstraction(a.grid.nx if hasattr(a.grid, "nx") else a.grid.n,
+                                a.grid.ny if hasattr(a.grid, "ny") else a.grid.n, a.row_ptr, a.col_idx, flags)
+
+
+def label(h, O, n_traj, kernel, host=False, stream=None):
+    n_props = O.shape[1]
+    if host:
+        L = np.full((n_traj, n_props), 9, np.uint8)
+        lbl.label_frame(h, np.ascontiguousarray(O), n_props, L, flags=kernel | lbl.HOST_PTRS)
+        return L
+    Od = torch.from_numpy(np.ascontiguousarray(O)).cuda()
+    Ld = torch.full((n_traj, n_props), 9, dtype=torch.uint8, device="cuda")
+    lbl.label_frame(h, Od, n_props, Ld, flags=kernel, stream=stream)
+    torch.cuda.synchronize()
+    return Ld.cpu().numpy()
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        raise AssertionError(f"{what}: {len(bad)} labels differ, first at {bad[:5].tolist()} "
+                             f"got {got[tuple(bad[0])]} want {want[tuple(bad[0])]}")
+
+
+class Csr:
+    """A T in CSR form on an nx x ny grid (cells row-major)."""
+
+    def __init__(self, nx, ny, row_ptr, col_idx):
+        self.grid = type("G", (), {"nx": nx, "ny": ny, "n_cells": nx * ny})()
+        self.row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
+        self.col_idx = np.ascontiguousarray(col_idx, np.uint32)
+        self.n_traj = len(self.row_ptr) - 1
+
+
+def random_csr(rng, n_traj, nx, ny, density, empty_frac=0.1, dup=True):
+    n_cells = nx * ny
+    counts = rng.binomial(n_cells, density, n_traj)
+    counts[rng.random(n_traj) < empty_frac] = 0
+    cols = [rng.choice(n_cells, size=c, replace=False) for c in counts]
+    if dup:
+        cols = [np.concatenate([c, c[: len(c) // 3]]) for c in cols]  # repeated ids, unsorted
+        cols = [rng.permutation(c) for c in cols]
+    counts = np.array([len(c) for c in cols])
+    rp = np.zeros(n_traj + 1, np.uint64)
+    np.cumsum(counts, out=rp[1:])
+    ci = np.concatenate(cols).astype(np.uint32) if counts.sum() else np.zeros(0, np.uint32)
+    return Csr(nx, ny, rp, ci)
+
+
+# ------------------------------------------------------------------ configs
+
+@pytest.fixture(scope="module")
+def cfg1():
+    say("generate 1k x 64^2 abstraction")
+    return gen.make_abstraction(1)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    say("generate 50k x 256^2 abstraction")
+    return gen.make_abstraction(2)
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_cfg1_every_kernel(cfg1, host):
+    a = cfg1
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    try:
+        for f in range(3):
+            O = gen.make_frame(1, a.grid, 8, frame=f)
+            want = expect(a, O)
+            for name, k in KERNELS.items():
+                say(f"cfg1 frame {f} kernel {name} host={host}")
+                assert_same(label(h, O, a.n_traj, k, host), want, f"cfg1/{name}/frame{f}")
+    finally:
+        lbl.free_abstraction(h)
+
+
+def test_cfg2_every_kernel(cfg2):
+    a = cfg2
+    say("cfg2 load with int8 copy")
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    try:
+        info = lbl.abstraction_info(h)
+        assert info["set_cells"] == len(np.unique(a.row_ptr[:-1]))*0 + int(a.row_ptr[-1])  # generator ids are unique
+        for f in range(2):
+            O = gen.make_frame(2, a.grid, 32, frame=f)
+            want = expect(a, O)
+            for name, k in KERNELS.items():
+                say(f"cfg2 frame {f} kernel {name}")
+                assert_same(label(h, O, a.n_traj, k), want, f"cfg2/{name}/frame{f}")
+    finally:
+        lbl.free_abstraction(h)
+
+
+@pytest.mark.parametrize("rho", [0.01, 0.10, 0.40])
+def test_cfg3_rows_subset_densities(rho):
+    say(f"cfg3 20k-row subset, rho={rho}")
+    a = gen.make_abstraction(3, n_traj=20000)
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    try:
+        O = gen.make_frame(3, a.grid, 64, frame=0, rho=rho)
+        want = expect(a, O)
+        for name, k in KERNELS.items():
+            say(f"cfg3 subset rho={rho} kernel {name}")
+            assert_same(label(h, O, a.n_traj, k), want, f"cfg3/{name}/rho{rho}")
+    finally:
+        lbl.free_abstraction(h)
+
+
+def test_cfg3_full_size_sampled_rows():
+    say("cfg3 full 200k x 512^2 x 64: generate")
+    a = gen.make_abstraction(3)
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
+    try:
+        info = lbl.abstraction_info(h)
+        assert info["set_cells"] == int(a.row_ptr[-1])
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(a.n_traj, 4096, replace=False)).astype(np.uint64)
+        rows[-1] = a.n_traj - 1
+        for rho in (0.01, 0.4):
+            O = gen.make_frame(3, a.grid, 64, frame=1, rho=rho)
+            for name in ("bits", "mfma"):
+                say(f"cfg3 full rho={rho} kernel {name}")
+                L = label(h, O, a.n_traj, KERNELS[name])
+                assert_same(L[rows.astype(np.int64)], expect(a, O, rows), f"cfg3-full/{name}/rho{rho}")
+                assert set(np.unique(L)) <= {0, 1}
+                # property at any size: a row with no swept cell has an all-false label
+                empty = np.nonzero(np.diff(a.row_ptr) == 0)[0]
+                assert not L[empty].any()
+    finally:
+        lbl.free_abstraction(h)
+
+
+# ------------------------------------------------------------------ edges
+
+@pytest.mark.parametrize("nx,ny,n_traj,n_props", [
+    (8, 8, 1, 1), (8, 8, 3, 64), (24, 8, 65, 7), (24, 40, 130, 17), (64, 64, 1007, 33),
+    (40, 24, 257, 63), (136, 8, 33, 16), (8, 136, 77, 2),
+])
+def test_ragged_shapes(nx, ny, n_traj, n_props):
+    rng = np.random.default_rng(nx * 1000 + ny + n_traj)
+    a = random_csr(rng, n_traj, nx, ny, 0.05)
+    say(f"ragged nx={nx} ny={ny} n_traj={n_traj} n_props={n_props}")
+    h = lbl.load_abstraction(nx, ny, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    try:
+        O = rng.integers(0, 256, (nx * ny, n_props)).astype(np.uint8)
+        O[rng.random(O.shape) < 0.9] = 0
+        want = expect(a, O)
+        for name, k in KERNELS.items():
+            assert_same(label(h, O, n_traj, k), want, f"ragged/{name}")
+    finally:
+        lbl.free_abstraction(h)
+
+
+def test_identity_and_single_cell_frames():
+    rng = np.random.default_rng(9)
+    nx = ny = 16
+    a = random_csr(rng, 200, nx, ny, 0.03)
+    T = np.zeros((200, nx * ny), np.uint8)
+    for t in range(200):
+        T[t, a.col_idx[a.row_ptr[t]:a.row_ptr[t + 1]].astype(np.int64)] = 1
+    h = lbl.load_abstraction(nx, ny, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    try:
+        for name, k in KERNELS.items():
+            say(f"identity frames kernel {name}")
+            for c0 in range(0, nx * ny, 64):
+                O = np.zeros((nx * ny, 64), np.uint8)
+                O[np.arange(c0, c0 + 64), np.arange(64)] = 1  # O = e_c columns
+                assert_same(label(h, O, 200, k), T[:, c0:c0 + 64], f"identity/{name}/{c0}")
+            ones = np.full((nx * ny, 3), 255, np.uint8)
+            assert_same(label(h, ones, 200, k), np.repeat((T.sum(1) > 0)[:, None], 3, 1).astype(np.uint8),
+                        f"ones/{name}")
+    finally:
+        lbl.free_abstraction(h)
+
+
+def test_dense_and_device_csr_loads_agree(cfg1):
+    a = cfg1
+    O = gen.make_frame(1, a.grid, 8, frame=5)
+    want = expect(a, O)
+    say("dense host load")
+    h1 = lbl.load_abstraction_dense(a.grid.n, a.grid.n, a.dense())
+    say("dense device load")
+    h2 = lbl.load_abstraction_dense(a.grid.n, a.grid.n, torch.from_numpy(a.dense()).cuda(), lbl.LOAD_INPUT_DEVICE)
+    say("csr device load")
+    h3 = lbl.load_abstraction(a.grid.n, a.grid.n, torch.from_numpy(a.row_ptr.astype(np.int64)).cuda(),
+                              torch.from_numpy(a.col_idx.astype(np.int32)).cuda(), lbl.LOAD_INPUT_DEVICE)
+    try:
+        for h in (h1, h2, h3):
+            assert_same(label(h, O, a.n_traj, lbl.KERNEL_BITS), want, "alt-load")
+    finally:
+        for h in (h1, h2, h3):
+            lbl.free_abstraction(h)
+
+
+def test_errors_on_device():
+    rng = np.random.default_rng(1)
+    a = random_csr(rng, 10, 8, 8, 0.2)
+    say("error paths")
+    bad = a.col_idx.copy()
+    bad[-1] = 64
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction(8, 8, a.row_ptr, bad)
+    assert e.value.status == lbl.EINVAL
+    h = lbl.load_abstraction(8, 8, a.row_ptr, a.col_idx)
+    try:
+        O = torch.zeros((64, 8), dtype=torch.uint8, device="cuda")
+        L = torch.zeros((10, 8), dtype=torch.uint8, device="cuda")
+        with pytest.raises(lbl.LblError):
+            lbl.label_frame(h, O, 65, L)
+        with pytest.raises(lbl.LblError):
+            lbl.label_frame(h, O, 0, L)
+        with pytest.raises(lbl.LblError) as e:
+            lbl.label_frame(h, O, 8, L, flags=lbl.KERNEL_MFMA_I8)
+        assert "KEEP_INT8" in str(e.value)
+    finally:
+        lbl.free_abstraction(h)
+
+
+def test_two_streams_same_abstraction(cfg1):
+    a = cfg1
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
+    try:
+        Os = [gen.make_frame(1, a.grid, 8, frame=10 + i) for i in range(2)]
+        wants = [expect(a, O) for O in Os]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        Od = [torch.from_numpy(O).cuda() for O in Os]
+        Ld = [torch.zeros((a.n_traj, 8), dtype=torch.uint8, device="cuda") for _ in Os]
+        torch.cuda.synchronize()
+        say("two streams")
+        for rep in range(5):
+            for i in range(2):
+                lbl.label_frame(h, Od[i], 8, Ld[i], flags=lbl.KERNEL_BITS, stream=streams[i])
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert_same(Ld[i].cpu().numpy(), wants[i], f"stream{i}")
+    finally:
+        lbl.free_abstraction(h)
