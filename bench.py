@@ -51,6 +51,12 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the kernel x density sweep")
     p.add_argument("--sweep-steps", type=int, default=10)
     p.add_argument("--no-pcie", action="store_true")
+    p.add_argument("--no-batch", action="store_true", help="skip the six-abstraction batched run")
+    p.add_argument("--batch-reps", type=int, default=10)
+    p.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    p.add_argument("--serve-seconds", type=float, default=5.0, help="seconds per arrival rate")
+    p.add_argument("--serve-rates", default="200,500,1000,2000")
+    p.add_argument("--serve-budget-mib", type=int, default=2048)
     return p.parse_args()
 
 
@@ -91,6 +97,155 @@ def traffic_from_profile(kernel_file: str, summary: str):
     if d.get("kernel_src_sha") != kernel_source_sha(kernel_file):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def load_batch_abstractions(lbl, gen):
+    """The six uneven abstractions (10k..200k trajectories on 128^2..512^2 grids)."""
+    out = []
+    for i in range(6):
+        a = gen.make_batch_abstraction(i)
+        h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
+        out.append((a, h))
+        log(f"  batch abstraction {i}: {a.n_traj} x {a.grid.n}^2")
+    return out
+
+
+def bench_batch(args, lbl, torch, gen, abss, stream):
+    """16 frames per abstraction (4..64 propositions, density 5..30%): one
+    persistent launch per batch versus one launch per frame."""
+    jobs = []
+    for i, (a, h) in enumerate(abss):
+        for k in range(16):
+            n_props = gen.batch_frame_props(4, i, k)
+            O = gen.make_frame(4, a.grid, n_props, frame=k, abstraction=i, rho_lo=0.05, rho_hi=0.30)
+            jobs.append((h, torch.from_numpy(O).cuda(), n_props,
+                         torch.empty((a.n_traj, n_props), dtype=torch.uint8, device="cuda")))
+    pairs = sum(abss[j // 16][0].n_traj * jobs[j][2] for j in range(len(jobs)))
+    # one frame per launch
+    for (h, Od, n, Ld) in jobs:
+        lbl.label_frame(h, Od, n, Ld, flags=lbl.KERNEL_BITS, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        for (h, Od, n, Ld) in jobs:
+            lbl.label_frame(h, Od, n, Ld, flags=lbl.KERNEL_BITS, stream=stream)
+    torch.cuda.synchronize()
+    single_s = (time.perf_counter() - t) / args.batch_reps
+    # batched: tune the tile for this shape class, then replay the cached graph
+    lbl.tune_batch(jobs, stream=stream)
+    lbl.label_batch(jobs, stream=stream)
+    torch.cuda.synchronize()
+    lbl.profile_enable(True)
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        lbl.label_batch(jobs, stream=stream)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t) / args.batch_reps
+    prof = lbl.profile_read()
+    lbl.profile_enable(False)
+    t_bytes = sum(lbl.abstraction_info(h)["bits_bytes"] for _, h in abss)
+    gpu_ms = prof["batch_ms"] / max(1, prof["batch_launches"])
+    return {"frames": len(jobs), "abstractions": [[a.n_traj, a.grid.n] for a, _ in abss],
+            "pairs_per_batch": pairs,
+            "one_frame_per_launch": {"ms": 1000 * single_s, "pairs_per_s": pairs / single_s},
+            "batched": {"ms": 1000 * batch_s, "gpu_ms": gpu_ms, "pairs_per_s": pairs / batch_s,
+                        "t_bytes": t_bytes, "t_gbs": t_bytes / (gpu_ms * 1e-3) / 1e9},
+            "speedup": single_s / batch_s}
+
+
+def bench_serve(args, lbl, torch, gen, abss):
+    """Poisson arrivals; each request one frame (8..64 propositions, density
+    5..30%) against one of the six resident abstractions, chosen uniformly."""
+    import queue
+    import threading
+
+    rng = np.random.default_rng([181002612, 5])
+    pool = []  # per abstraction: list of (Od, n_props)
+    for i, (a, h) in enumerate(abss):
+        frames = []
+        for k in range(8):
+            n_props = int(rng.integers(8, 65))
+            O = gen.make_frame(5, a.grid, n_props, frame=k, abstraction=i, rho_lo=0.05, rho_hi=0.30)
+            frames.append((torch.from_numpy(O).cuda(), n_props))
+        pool.append(frames)
+    ring = 48
+    Lbuf = [[torch.empty(a.n_traj * 64, dtype=torch.uint8, device="cuda") for _ in range(ring)] for a, _ in abss]
+    torch.cuda.synchronize()
+    results = []
+    for lam in [float(x) for x in args.serve_rates.split(",")]:
+        s = lbl.serve_start(hbm_budget_bytes=args.serve_budget_mib << 20, max_batch_frames=16, max_wait_us=0,
+                            max_queue=8192, n_streams=3)
+        free = [queue.Queue() for _ in abss]
+        for q in free:
+            for k in range(ring):
+                q.put(k)
+        inflight = queue.Queue()
+        samples, errors = [], []
+        n_req = int(lam * args.serve_seconds)
+        gaps = rng.exponential(1.0 / lam, n_req)
+        choice = rng.integers(0, len(abss), n_req)
+        fpick = rng.integers(0, 8, n_req)
+        sample_every = 100
+
+        def submitter():
+            t0 = time.perf_counter()
+            t_next = 0.0
+            for r in range(n_req):
+                t_next += gaps[r]
+                dt = t0 + t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                i, f = int(choice[r]), int(fpick[r])
+                Od, n_props = pool[i][f]
+                k = free[i].get()
+                Ld = Lbuf[i][k][: abss[i][0].n_traj * n_props]
+                try:
+                    tk = lbl.serve_submit(s, abss[i][1], Od, n_props, Ld)
+                except lbl.LblError as e:
+                    errors.append(str(e))
+                    free[i].put(k)
+                    continue
+                inflight.put((tk, i, k, f, r))
+            inflight.put(None)
+
+        def waiter():
+            while True:
+                item = inflight.get()
+                if item is None:
+                    return
+                tk, i, k, f, r = item
+                st = lbl.serve_wait(s, tk)
+                if st != lbl.OK:
+                    errors.append(f"ticket {tk}: {st}")
+                elif r % sample_every == 0:
+                    n_props = pool[i][f][1]
+                    samples.append((i, f, Lbuf[i][k][: abss[i][0].n_traj * n_props].clone()))
+                free[i].put(k)
+
+        ts = [threading.Thread(target=submitter), threading.Thread(target=waiter)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        st = lbl.serve_stats(s)
+        lbl.serve_stop(s)
+        # identity: each sampled request labeled alone gives the same bytes
+        same = 0
+        for i, f, Lmix in samples:
+            Od, n_props = pool[i][f]
+            La = torch.empty_like(Lmix)
+            lbl.label_frame(abss[i][1], Od, n_props, La, flags=lbl.KERNEL_BITS)
+            torch.cuda.synchronize()
+            same += int(torch.equal(La, Lmix))
+        results.append({"rate_per_s": lam, "seconds": args.serve_seconds, "submitted": st["submitted"],
+                        "completed": st["completed"], "rejected": st["rejected"], "failed": st["failed"],
+                        "batches": st["batches"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                        "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+                        "req_per_s": st["completed"] / st["wall_s"], "pairs_per_s": st["pairs_per_s"],
+                        "max_in_flight": st["max_in_flight"], "budget_high_water": st["budget_high_water"],
+                        "identity_checked": len(samples), "identity_same": same, "errors": errors[:3]})
+        log("serve", results[-1])
+    return results
 
 
 def main():
@@ -202,6 +357,17 @@ def main():
                 log("sweep", sweep[-1])
         lbl.free_abstraction(h8)
         out["kernel_sweep"] = sweep
+
+    if not (args.no_batch and args.no_serve):
+        log("load the six batch abstractions")
+        abss = load_batch_abstractions(lbl, gen)
+        if not args.no_batch:
+            out["batch"] = bench_batch(args, lbl, torch, gen, abss, stream)
+            log("batch", out["batch"])
+        if not args.no_serve:
+            out["serve"] = bench_serve(args, lbl, torch, gen, abss)
+        for _, hb in abss:
+            lbl.free_abstraction(hb)
 
     if not args.no_cpu:
         import oracle  # the CPU baseline leg: oracle as it stands, all host threads

@@ -145,15 +145,21 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
 
 /*
  * Label many frames, possibly against different abstractions, in one
- * persistent-kernel launch.  Each job is one frame as in lbl_label_frame.
- * Jobs on the same abstraction share each pass over T: their propositions
- * are concatenated (at most LBL_BATCH_MAX_PROPS per abstraction per call).
+ * persistent-kernel launch.  Each job is one frame as in lbl_label_frame
+ * (device pointers; flags must be 0).  Jobs on the same abstraction share
+ * each pass over T: their propositions are concatenated, up to
+ * LBL_BATCH_MAX_PROPS per pass (more propositions on one abstraction take
+ * further passes in the same launch).  Workgroups pull (abstraction, row
+ * range) items from a queue, largest first.
+ *
  * The whole pipeline of a batch (O packing, labeling) is recorded once as a
- * HIP graph keyed by the batch's shape and buffers and replayed when the same
- * batch is submitted again.  Results are identical to labeling each job alone.
+ * HIP graph keyed by (hip_stream, jobs) and replayed when the same batch is
+ * submitted again on that stream; the graph owns its tables and packed masks
+ * (up to 8 graphs are cached; the oldest is released after a device
+ * synchronization).  Results are identical to labeling each job alone.
  *
  * Errors: as lbl_label_frame for every job, plus LBL_EINVAL for n_jobs == 0
- * or more than LBL_BATCH_MAX_PROPS propositions on one abstraction.
+ * or nonzero flags.
  */
 typedef struct {
     lbl_abs_t a;
@@ -179,6 +185,12 @@ lbl_status lbl_label_batch(const lbl_job *jobs, size_t n_jobs, uint32_t flags, v
  */
 lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint32_t density_pct,
                     void *hip_stream);
+/* Time the batch kernel's tile shapes (rows per work item, wavefronts per
+ * workgroup, loads in flight) on this batch and record the fastest for its
+ * shape class (the multiset of (words per row, lane groups) of its passes);
+ * later lbl_label_batch calls of that class use it.  Runs the batch several
+ * times (the jobs' L buffers are overwritten); synchronizes hip_stream. */
+lbl_status lbl_tune_batch(const lbl_job *jobs, size_t n_jobs, void *hip_stream);
 lbl_status lbl_tune_save(const char *path);
 lbl_status lbl_tune_load(const char *path);
 /* Describe the choice AUTO makes for (a, n_props) into buf (NUL-terminated). */
@@ -234,10 +246,12 @@ lbl_status lbl_serve_stop(lbl_server_t s);
  * disabling resets the totals.  Not for use under graph capture.
  */
 typedef struct {
-    uint64_t pack_launches;   /* O packing kernels timed */
-    uint64_t label_launches;  /* labeling kernels timed */
+    uint64_t pack_launches;   /* O packing kernels timed (lbl_label_frame) */
+    uint64_t label_launches;  /* labeling kernels timed (lbl_label_frame) */
+    uint64_t batch_launches;  /* whole batches timed (lbl_label_batch: packing + labeling) */
     double pack_ms;           /* summed durations */
     double label_ms;
+    double batch_ms;
 } lbl_profile;
 
 lbl_status lbl_profile_enable(int on);

@@ -1,0 +1,108 @@
+// Batched labeling: many frames over several abstractions in one persistent
+// launch.  Used by lbl_label_batch (graph-cached) and by the server (direct).
+#pragma once
+
+#include "lbl_internal.h"
+
+namespace lbl {
+
+// Per output lane (one proposition column of one frame).
+struct LaneDesc {
+    const uint8_t *O;  // &O_job[p] (cell c at O[c * n_props]), null for an unused lane
+    uint8_t *L;        // &L_job[p] (row t at L[t * n_props]), null for an unused lane
+    uint32_t n_props;
+    uint32_t pad;
+};
+
+// Per abstraction group: all jobs on one abstraction, propositions
+// concatenated into G64 groups of 64 lanes.
+struct GroupDesc {
+    const uint64_t *T;
+    const uint32_t *word_cell;
+    uint64_t *Ow;             // [n_words][G64][64] packed masks
+    const LaneDesc *lanes;    // [G64][64]
+    uint64_t n_traj;
+    uint32_t row_stride;
+    uint32_t n_words;
+    uint32_t G64;
+    uint32_t pad;
+};
+
+struct WorkItem {
+    uint32_t group;
+    uint32_t pad;
+    uint64_t row0, row1;
+};
+
+struct BatchTile {
+    int unroll = 8;
+    int waves_per_block = 4;
+    int rows_per_item = 128;
+};
+
+struct JobRef {
+    lbl_abs *a;
+    const uint8_t *O;
+    uint32_t n_props;
+    uint8_t *L;
+};
+
+// Host-side description of one launch: groups, lane tables, work items.
+struct BatchPlan {
+    std::vector<GroupDesc> groups;  // Ow and lanes fields are offsets until bound
+    std::vector<LaneDesc> lanes;    // all groups' lane tables, concatenated
+    std::vector<size_t> lane_off;   // first lane of each group
+    std::vector<size_t> ow_off;     // byte offset of each group's Ow in the Ow region
+    std::vector<WorkItem> items;
+    size_t ow_bytes = 0;
+    uint32_t max_g64 = 1;
+    uint64_t pack_units = 0;        // sum over groups of n_words * G64
+    BatchTile tile;
+    uint64_t pairs = 0;             // labeled (trajectory, proposition) pairs
+    std::string shape_key;
+
+    bool finalized = false;         // tile set and items made
+
+    // bytes of device memory the launch needs (tables + packed masks); only
+    // meaningful once the plan is finalized
+    size_t device_bytes() const;
+};
+
+// Build the plan (validates jobs; device >= 0 also requires every abstraction
+// to live on that device).  Jobs on one abstraction are split into passes of
+// at most LBL_BATCH_MAX_PROPS propositions.  Host-only.
+lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *out);
+
+// Fix the tile and make the work items (row ranges, costliest groups first).
+// Must precede device_bytes() and bind_batch().  Host-only.
+void plan_finalize(BatchPlan &plan, const BatchTile &tile);
+
+// Device buffer holding the plan's tables and masks, laid out by bind_batch.
+struct BatchBuffers {
+    uint8_t *base = nullptr;
+    size_t bytes = 0;
+    GroupDesc *d_groups = nullptr;
+    WorkItem *d_items = nullptr;
+    LaneDesc *d_lanes = nullptr;
+    uint64_t *d_pack_prefix = nullptr;
+    uint32_t *d_counter = nullptr;
+    uint64_t *d_ow = nullptr;
+};
+
+// Lay the finalized plan out in `base` (capacity bytes of device memory) and
+// fill `host_image` with the bytes to copy to base (tables; masks excluded).
+// LBL_EINVAL if the plan is not finalized, LBL_ENOMEM if it needs more than
+// capacity.  Host-only.
+lbl_status bind_batch(const BatchPlan &plan, uint8_t *base, size_t capacity, BatchBuffers *bufs,
+                      std::vector<uint8_t> *host_image);
+size_t batch_table_bytes(const BatchPlan &plan);
+
+// Enqueue: counter reset, O packing for every job, persistent label kernel.
+lbl_status enqueue_batch(const BatchPlan &plan, const BatchBuffers &bufs, hipStream_t s);
+
+int device_cu_count();
+
+// Tile recorded by lbl_tune_batch for a shape class (the default if none).
+BatchTile batch_tile_for(const std::string &shape_key);
+
+}  // namespace lbl

@@ -1,0 +1,487 @@
+// Batched labeling in one persistent launch.
+//
+// Jobs on the same abstraction form a group: their propositions are laid
+// side by side in G64 lane groups of 64, so one pass over T labels all of
+// them (T is read once per batch, not once per frame).  The O packing of
+// every job is one kernel; the labeling is one persistent kernel whose
+// workgroups pull (group, row range) items from an atomic counter, largest
+// items first, so uneven abstractions share the GPU without a tail of idle
+// CUs.  lbl_label_batch records the whole pipeline once as a HIP graph keyed
+// by (stream, jobs, flags) and replays it.
+#include <algorithm>
+#include <cstring>
+#include <list>
+#include <map>
+#include <memory>
+
+#include "batch.h"
+#include "profile.h"
+
+namespace lbl {
+
+namespace {
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int src)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Zero the work counter (a kernel, not a memset node, so graph replays are safe).
+__global__ void k_zero(uint32_t *counter) { *counter = 0u; }
+
+// One wavefront per (group, word, lane group): lane l packs the 64 cells of
+// the word for the proposition column that lane (gi, l) stands for.
+__global__ void __launch_bounds__(256)
+k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
+             uint64_t n_units)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t u = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < n_units; u += waves) {
+        uint32_t gidx = 0;
+        while (gidx + 1 < n_groups && prefix[gidx + 1] <= u) ++gidx;
+        const GroupDesc g = groups[gidx];
+        const uint64_t local = u - prefix[gidx];
+        const uint32_t w = (uint32_t)(local / g.G64), gi = (uint32_t)(local % g.G64);
+        const LaneDesc d = g.lanes[gi * 64 + lane];
+        uint64_t m = 0;
+        if (d.O) {
+            const uint32_t *wc = g.word_cell + (uint64_t)w * 64;
+#pragma unroll 16
+            for (uint32_t b = 0; b < 64; ++b) m |= (uint64_t)(d.O[(uint64_t)wc[b] * d.n_props] != 0) << b;
+        }
+        g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
+    }
+}
+
+// Persistent labeling kernel.  Bit gi of lane l's accumulator is the label of
+// the proposition column (gi, l) for the current row.
+template <int UNROLL, int MAXG>
+__global__ void __launch_bounds__(1024)
+k_label_batch(const GroupDesc *__restrict__ groups, const WorkItem *__restrict__ items, uint32_t n_items,
+              uint32_t *counter)
+{
+    __shared__ uint32_t s_item;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= n_items) return;  // uniform: every wavefront of the block leaves together
+        const WorkItem item = items[it];
+        const GroupDesc g = groups[item.group];
+        const uint32_t G = g.G64;
+        uint32_t vmask = 0;
+#pragma unroll
+        for (int gi = 0; gi < MAXG; ++gi)
+            if ((uint32_t)gi < G && g.lanes[gi * 64 + lane].L) vmask |= 1u << gi;
+        const uint32_t n_pairs = (g.n_words + 1) >> 1;
+        for (uint64_t row = item.row0 + wave; row < item.row1; row += n_waves) {
+            const u64x2 *Tr = reinterpret_cast<const u64x2 *>(g.T + row * (uint64_t)g.row_stride);
+            uint32_t acc = 0;
+            for (uint32_t base = 0; base < n_pairs; base += 64 * UNROLL) {
+                u64x2 v[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const uint32_t i = base + u * 64 + lane;
+                    v[u] = i < n_pairs ? __builtin_nontemporal_load(Tr + i) : u64x2{0ull, 0ull};
+                }
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    uint64_t nz = __ballot((v[u].x | v[u].y) != 0ull);
+                    while (nz) {
+                        const int src = __builtin_ctzll(nz);
+                        nz &= nz - 1ull;
+                        const uint64_t wi = 2ull * (base + (uint32_t)(u * 64 + src));
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const uint64_t word = readlane64(h ? v[u].y : v[u].x, src);
+                            if (!word) continue;
+                            const uint64_t *o = g.Ow + (wi + h) * G * 64 + lane;
+#pragma unroll
+                            for (int gi = 0; gi < MAXG; ++gi)
+                                if ((uint32_t)gi < G) acc |= (uint32_t)((word & o[gi * 64]) != 0ull) << gi;
+                        }
+                    }
+                }
+                if (__ballot((acc & vmask) != vmask) == 0ull) break;  // every column already hit
+            }
+#pragma unroll
+            for (int gi = 0; gi < MAXG; ++gi) {
+                if ((uint32_t)gi >= G) break;
+                const LaneDesc d = g.lanes[gi * 64 + lane];
+                if (d.L) d.L[row * d.n_props] = (uint8_t)((acc >> gi) & 1u);
+            }
+        }
+    }
+}
+
+template <int U, int G>
+hipError_t launch_label(const BatchBuffers &b, uint32_t n_items, int wpb, unsigned blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_label_batch<U, G>), dim3(blocks), dim3(64 * wpb), 0, s, b.d_groups, b.d_items, n_items,
+                       b.d_counter);
+    return hipGetLastError();
+}
+
+template <int U>
+hipError_t launch_label_g(const BatchBuffers &b, uint32_t n_items, uint32_t maxg, int wpb, unsigned blocks,
+                          hipStream_t s)
+{
+    if (maxg <= 1) return launch_label<U, 1>(b, n_items, wpb, blocks, s);
+    if (maxg <= 2) return launch_label<U, 2>(b, n_items, wpb, blocks, s);
+    if (maxg <= 4) return launch_label<U, 4>(b, n_items, wpb, blocks, s);
+    if (maxg <= 8) return launch_label<U, 8>(b, n_items, wpb, blocks, s);
+    return launch_label<U, 16>(b, n_items, wpb, blocks, s);
+}
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+int device_cu_count()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+size_t batch_table_bytes(const BatchPlan &p)
+{
+    return up256(p.groups.size() * sizeof(GroupDesc)) + up256(p.items.size() * sizeof(WorkItem)) +
+           up256(p.lanes.size() * sizeof(LaneDesc)) + up256((p.groups.size() + 1) * sizeof(uint64_t)) + 256;
+}
+
+size_t BatchPlan::device_bytes() const { return batch_table_bytes(*this) + ow_bytes; }
+
+lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *out)
+{
+    LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
+    std::vector<lbl_abs *> order;
+    std::map<lbl_abs *, std::vector<size_t>> by_abs;
+    for (size_t j = 0; j < n_jobs; ++j) {
+        const JobRef &r = jobs[j];
+        LBL_REQUIRE(r.a != nullptr, "job " + std::to_string(j) + ": abstraction is null");
+        LBL_REQUIRE(r.O != nullptr && r.L != nullptr, "job " + std::to_string(j) + ": O or L is null");
+        LBL_REQUIRE(r.n_props >= 1 && r.n_props <= 64, "job " + std::to_string(j) + ": n_props must be in [1, 64]");
+        LBL_REQUIRE(device < 0 || r.a->device == device, "job " + std::to_string(j) + ": abstraction lives on another device");
+        if (!by_abs.count(r.a)) order.push_back(r.a);
+        by_abs[r.a].push_back(j);
+    }
+    BatchPlan &p = *out;
+    p = BatchPlan{};
+    std::vector<std::string> keys;
+    for (lbl_abs *a : order) {
+        const auto &js = by_abs[a];
+        size_t k = 0;
+        while (k < js.size()) {
+            // one pass: consecutive jobs while the concatenated columns fit
+            uint32_t P = 0;
+            size_t k1 = k;
+            while (k1 < js.size() && P + jobs[js[k1]].n_props <= LBL_BATCH_MAX_PROPS) P += jobs[js[k1++]].n_props;
+            GroupDesc g{};
+            g.T = a->T_bits;
+            g.word_cell = a->d_word_cell;
+            g.n_traj = a->n_traj;
+            g.row_stride = a->row_stride;
+            g.n_words = a->n_words;
+            g.G64 = (P + 63) / 64;
+            p.lane_off.push_back(p.lanes.size());
+            p.lanes.resize(p.lanes.size() + (size_t)g.G64 * 64, LaneDesc{nullptr, nullptr, 0, 0});
+            size_t q = p.lane_off.back();
+            for (size_t m = k; m < k1; ++m) {
+                const JobRef &r = jobs[js[m]];
+                for (uint32_t c = 0; c < r.n_props; ++c, ++q) p.lanes[q] = LaneDesc{r.O + c, r.L + c, r.n_props, 0};
+                p.pairs += a->n_traj * r.n_props;
+            }
+            p.ow_off.push_back(p.ow_bytes);
+            p.ow_bytes += up256((size_t)a->n_words * g.G64 * 64 * sizeof(uint64_t));
+            p.pack_units += (uint64_t)a->n_words * g.G64;
+            p.max_g64 = std::max(p.max_g64, g.G64);
+            p.groups.push_back(g);
+            keys.push_back("W" + std::to_string(a->n_words) + "G" + std::to_string(g.G64));
+            k = k1;
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    for (auto &s : keys) p.shape_key += s + ";";
+    return LBL_OK;
+}
+
+void plan_finalize(BatchPlan &p, const BatchTile &tile)
+{
+    p.tile = tile;
+    p.items.clear();
+    std::vector<uint32_t> idx(p.groups.size());
+    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    auto cost = [&](uint32_t g) { return (double)p.groups[g].n_words * (4.0 + p.groups[g].G64); };
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
+    const uint64_t R = (uint64_t)std::max(1, p.tile.rows_per_item);
+    for (uint32_t g : idx)
+        for (uint64_t r0 = 0; r0 < p.groups[g].n_traj; r0 += R)
+            p.items.push_back(WorkItem{g, 0, r0, std::min(r0 + R, p.groups[g].n_traj)});
+    p.finalized = true;
+}
+
+lbl_status bind_batch(const BatchPlan &p, uint8_t *base, size_t capacity, BatchBuffers *b, std::vector<uint8_t> *img)
+{
+    LBL_REQUIRE(p.finalized, "batch plan bound before it was finalized");
+    size_t off = 0;
+    const size_t o_groups = off;
+    off += up256(p.groups.size() * sizeof(GroupDesc));
+    const size_t o_items = off;
+    off += up256(p.items.size() * sizeof(WorkItem));
+    const size_t o_lanes = off;
+    off += up256(p.lanes.size() * sizeof(LaneDesc));
+    const size_t o_prefix = off;
+    off += up256((p.groups.size() + 1) * sizeof(uint64_t));
+    const size_t o_counter = off;
+    off += 256;
+    const size_t o_ow = off;
+    if (off + p.ow_bytes > capacity || off + p.ow_bytes != p.device_bytes()) {
+        set_error("batch layout needs " + std::to_string(off + p.ow_bytes) + " bytes, buffer holds " +
+                  std::to_string(capacity));
+        return LBL_ENOMEM;
+    }
+    b->base = base;
+    b->bytes = off + p.ow_bytes;
+    b->d_groups = reinterpret_cast<GroupDesc *>(base + o_groups);
+    b->d_items = reinterpret_cast<WorkItem *>(base + o_items);
+    b->d_lanes = reinterpret_cast<LaneDesc *>(base + o_lanes);
+    b->d_pack_prefix = reinterpret_cast<uint64_t *>(base + o_prefix);
+    b->d_counter = reinterpret_cast<uint32_t *>(base + o_counter);
+    b->d_ow = reinterpret_cast<uint64_t *>(base + o_ow);
+    img->assign(o_ow, 0);
+    std::vector<GroupDesc> gs = p.groups;
+    std::vector<uint64_t> prefix(p.groups.size() + 1, 0);
+    for (size_t g = 0; g < gs.size(); ++g) {
+        gs[g].Ow = reinterpret_cast<uint64_t *>(base + o_ow + p.ow_off[g]);
+        gs[g].lanes = b->d_lanes + p.lane_off[g];
+        prefix[g + 1] = prefix[g] + (uint64_t)gs[g].n_words * gs[g].G64;
+    }
+    memcpy(img->data() + o_groups, gs.data(), gs.size() * sizeof(GroupDesc));
+    memcpy(img->data() + o_items, p.items.data(), p.items.size() * sizeof(WorkItem));
+    memcpy(img->data() + o_lanes, p.lanes.data(), p.lanes.size() * sizeof(LaneDesc));
+    memcpy(img->data() + o_prefix, prefix.data(), prefix.size() * sizeof(uint64_t));
+    return LBL_OK;
+}
+
+lbl_status enqueue_batch(const BatchPlan &p, const BatchBuffers &b, hipStream_t s)
+{
+    LBL_REQUIRE(p.finalized && b.base != nullptr, "batch enqueued before it was bound");
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, b.d_counter);
+    LBL_HIP_TRY(hipGetLastError());
+    const uint64_t pack_blocks = std::min<uint64_t>((p.pack_units + 3) / 4, 1u << 16);
+    hipLaunchKernelGGL(k_pack_batch, dim3((unsigned)std::max<uint64_t>(pack_blocks, 1)), dim3(256), 0, s, b.d_groups,
+                       b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units);
+    LBL_HIP_TRY(hipGetLastError());
+    const int wpb = p.tile.waves_per_block;
+    LBL_REQUIRE(wpb >= 1 && wpb <= 16, "batch tile: waves_per_block out of range");
+    const uint32_t n_items = (uint32_t)p.items.size();
+    const unsigned occupancy = (unsigned)std::max(1, 32 / wpb);  // resident workgroups per CU
+    const unsigned blocks = (unsigned)std::min<uint64_t>(n_items, (uint64_t)device_cu_count() * occupancy);
+    if (blocks == 0) return LBL_OK;
+    hipError_t e;
+    switch (p.tile.unroll) {
+    case 4: e = launch_label_g<4>(b, n_items, p.max_g64, wpb, blocks, s); break;
+    case 8: e = launch_label_g<8>(b, n_items, p.max_g64, wpb, blocks, s); break;
+    default: LBL_REQUIRE(false, "batch tile: unroll must be 4 or 8");
+    }
+    LBL_HIP_TRY(e);
+    return LBL_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+namespace {
+std::mutex g_tile_mu;
+std::map<std::string, BatchTile> g_tiles;
+
+BatchTile tuned_tile(const std::string &key)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find(key);
+    return it == g_tiles.end() ? BatchTile{} : it->second;
+}
+
+// ---------------------------------------------------------------- graph cache
+
+struct GraphEntry {
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    std::vector<JobRef> jobs;
+    BatchPlan plan;
+    BatchBuffers bufs;
+    void *dmem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+std::mutex g_graph_mu;
+std::list<std::unique_ptr<GraphEntry>> g_graphs;  // most recent first
+const size_t kMaxGraphs = 8;
+
+bool same_jobs(const std::vector<JobRef> &a, const JobRef *b, size_t n)
+{
+    if (a.size() != n) return false;
+    for (size_t i = 0; i < n; ++i)
+        if (a[i].a != b[i].a || a[i].O != b[i].O || a[i].n_props != b[i].n_props || a[i].L != b[i].L) return false;
+    return true;
+}
+
+void destroy_entry(GraphEntry *e)
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(e->device);
+    (void)hipDeviceSynchronize();
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->dmem) (void)hipFree(e->dmem);
+    (void)hipSetDevice(cur);
+}
+
+lbl_status build_entry(GraphEntry *e)
+{
+    const size_t bytes = e->plan.device_bytes();
+    LBL_HIP_TRY(hipMalloc(&e->dmem, bytes));
+    std::vector<uint8_t> img;
+    lbl_status bst = bind_batch(e->plan, static_cast<uint8_t *>(e->dmem), bytes, &e->bufs, &img);
+    if (bst != LBL_OK) return bst;
+    LBL_HIP_TRY(hipMemcpy(e->dmem, img.data(), img.size(), hipMemcpyHostToDevice));
+    hipStream_t cs = nullptr;
+    LBL_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    lbl_status st = LBL_OK;
+    if (err == hipSuccess) {
+        st = enqueue_batch(e->plan, e->bufs, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        e->graph = g;
+        if (st == LBL_OK && e2 != hipSuccess) err = e2;
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != LBL_OK) return st;
+    LBL_HIP_TRY(err);
+    LBL_HIP_TRY(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+    return LBL_OK;
+}
+
+}  // namespace
+
+BatchTile batch_tile_for(const std::string &key) { return tuned_tile(key); }
+
+void set_batch_tile(const std::string &key, const BatchTile &t)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tiles[key] = t;
+}
+
+lbl_status label_batch_graph(const JobRef *jobs, size_t n_jobs, uint32_t flags, hipStream_t s, const BatchTile *force)
+{
+    int cur = 0;
+    LBL_HIP_TRY(hipGetDevice(&cur));
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphEntry *hit = nullptr;
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
+        GraphEntry *e = it->get();
+        if (e->stream == s && e->flags == flags && e->device == cur && same_jobs(e->jobs, jobs, n_jobs) &&
+            (!force || (e->plan.tile.unroll == force->unroll && e->plan.tile.waves_per_block == force->waves_per_block &&
+                        e->plan.tile.rows_per_item == force->rows_per_item))) {
+            g_graphs.splice(g_graphs.begin(), g_graphs, it);
+            hit = e;
+            break;
+        }
+    }
+    if (!hit) {
+        std::unique_ptr<GraphEntry> e(new GraphEntry());
+        e->stream = s;
+        e->flags = flags;
+        e->device = cur;
+        e->jobs.assign(jobs, jobs + n_jobs);
+        lbl_status st = plan_batch(jobs, n_jobs, cur, &e->plan);
+        if (st != LBL_OK) return st;
+        plan_finalize(e->plan, force ? *force : tuned_tile(e->plan.shape_key));
+        st = build_entry(e.get());
+        if (st != LBL_OK) {
+            destroy_entry(e.get());
+            return st;
+        }
+        while (g_graphs.size() >= kMaxGraphs) {
+            destroy_entry(g_graphs.back().get());
+            g_graphs.pop_back();
+        }
+        g_graphs.push_front(std::move(e));
+        hit = g_graphs.front().get();
+    }
+    void *span = span_begin(s);
+    LBL_HIP_TRY(hipGraphLaunch(hit->exec, s));
+    span_end(span, s, 2);
+    return LBL_OK;
+}
+
+}  // namespace lbl
+
+using namespace lbl;
+
+extern "C" {
+
+lbl_status lbl_label_batch(const lbl_job *jobs, size_t n_jobs, uint32_t flags, void *hip_stream)
+{
+    clear_error();
+    LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
+    LBL_REQUIRE(flags == 0, "lbl_label_batch takes device pointers and no flags");
+    std::vector<JobRef> refs(n_jobs);
+    for (size_t j = 0; j < n_jobs; ++j) refs[j] = JobRef{jobs[j].a, jobs[j].O, jobs[j].n_props, jobs[j].L};
+    return label_batch_graph(refs.data(), n_jobs, flags, reinterpret_cast<hipStream_t>(hip_stream), nullptr);
+}
+
+lbl_status lbl_tune_batch(const lbl_job *jobs, size_t n_jobs, void *hip_stream)
+{
+    clear_error();
+    LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    std::vector<JobRef> refs(n_jobs);
+    for (size_t j = 0; j < n_jobs; ++j) refs[j] = JobRef{jobs[j].a, jobs[j].O, jobs[j].n_props, jobs[j].L};
+    BatchPlan probe;
+    int cur = 0;
+    LBL_HIP_TRY(hipGetDevice(&cur));
+    lbl_status st = plan_batch(refs.data(), n_jobs, cur, &probe);
+    if (st != LBL_OK) return st;
+    hipEvent_t e0, e1;
+    LBL_HIP_TRY(hipEventCreate(&e0));
+    LBL_HIP_TRY(hipEventCreate(&e1));
+    BatchTile best;
+    float best_ms = 1e30f;
+    for (int u : {4, 8})
+        for (int w : {4, 8, 16})
+            for (int r : {32, 128, 512}) {
+                BatchTile t{u, w, r};
+                st = label_batch_graph(refs.data(), n_jobs, 0, s, &t);  // build + warm-up
+                if (st != LBL_OK) break;
+                LBL_HIP_TRY(hipEventRecord(e0, s));
+                for (int k = 0; k < 3; ++k) label_batch_graph(refs.data(), n_jobs, 0, s, &t);
+                LBL_HIP_TRY(hipEventRecord(e1, s));
+                LBL_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                LBL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBL_OK) return st;
+    set_batch_tile(probe.shape_key, best);
+    return LBL_OK;
+}
+
+}  // extern "C"

@@ -32,7 +32,7 @@ BATCH_MAX_PROPS = 1024
 
 EXPORTS = (
     "lbl_load_abstraction", "lbl_load_abstraction_dense", "lbl_free_abstraction", "lbl_abstraction_info",
-    "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
+    "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_batch", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
     "lbl_serve_start", "lbl_serve_submit", "lbl_serve_wait", "lbl_serve_stats_get", "lbl_serve_stop",
     "lbl_cell_position", "lbl_last_error", "lbl_version", "lbl_profile_enable", "lbl_profile_read",
 )
@@ -62,7 +62,8 @@ class Job(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("pack_launches", ctypes.c_uint64), ("label_launches", ctypes.c_uint64),
-                ("pack_ms", ctypes.c_double), ("label_ms", ctypes.c_double)]
+                ("batch_launches", ctypes.c_uint64), ("pack_ms", ctypes.c_double), ("label_ms", ctypes.c_double),
+                ("batch_ms", ctypes.c_double)]
 
 
 class ServeCfg(ctypes.Structure):
@@ -106,6 +107,7 @@ def lib():
         "lbl_label_frame": [vp, vp, u32, vp, u32, vp],
         "lbl_label_batch": [ctypes.POINTER(Job), ctypes.c_size_t, u32, vp],
         "lbl_tune": [vp, vp, u32, u32, vp],
+        "lbl_tune_batch": [ctypes.POINTER(Job), ctypes.c_size_t, vp],
         "lbl_tune_save": [ctypes.c_char_p],
         "lbl_tune_load": [ctypes.c_char_p],
         "lbl_tune_describe": [vp, u32, ctypes.c_char_p, ctypes.c_size_t],
@@ -219,14 +221,22 @@ def label_frame(a: int, O, n_props: int, L, flags: int = 0, stream=None) -> None
 
 def label_batch(jobs, flags: int = 0, stream=None) -> None:
     """jobs: sequence of (abstraction, O, n_props, L)."""
-    arr = (Job * len(jobs))()
-    for i, (a, O, n_props, L) in enumerate(jobs):
-        arr[i] = Job(a, _addr(O), int(n_props), _addr(L))
-    _check(lib().lbl_label_batch(arr, len(jobs), flags, _stream(stream)))
+    _check(lib().lbl_label_batch(_jobs(jobs), len(jobs), flags, _stream(stream)))
 
 
 def tune(a: int, O_sample, n_props: int, density_pct: int = 10, stream=None) -> None:
     _check(lib().lbl_tune(a, _addr(O_sample), n_props, density_pct, _stream(stream)))
+
+
+def _jobs(jobs):
+    arr = (Job * len(jobs))()
+    for i, (a, O, n_props, L) in enumerate(jobs):
+        arr[i] = Job(a, _addr(O), int(n_props), _addr(L))
+    return arr
+
+
+def tune_batch(jobs, stream=None) -> None:
+    _check(lib().lbl_tune_batch(_jobs(jobs), len(jobs), _stream(stream)))
 
 
 def tune_save(path: str) -> None:
