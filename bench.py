@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "labeled traj-prop pairs/s & % roofline, 200k×512²×64; served p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -44,7 +45,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--frames", type=int, default=8, help="distinct frames cycled through the steps")
     p.add_argument("--rho", type=float, default=0.01, help="O cell density of every proposition")
-    p.add_argument("--kernel", default="auto", choices=["auto", "bits", "mfma", "mfma_i8"])
+    p.add_argument("--kernel", default="auto", choices=["auto", "sparse", "bits", "mfma", "mfma_i8"])
     p.add_argument("--n-traj", type=int, default=200000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -62,7 +63,7 @@ def parse():
 
 def kernel_flag(lbl, name):
     return {"auto": lbl.KERNEL_AUTO, "bits": lbl.KERNEL_BITS, "mfma": lbl.KERNEL_MFMA,
-            "mfma_i8": lbl.KERNEL_MFMA_I8}[name]
+            "mfma_i8": lbl.KERNEL_MFMA_I8, "sparse": lbl.KERNEL_SPARSE}[name]
 
 
 def timed_steps(lbl, torch, h, Os, n_props, L, flags, steps, stream):
@@ -97,6 +98,37 @@ def traffic_from_profile(kernel_file: str, summary: str):
     if d.get("kernel_src_sha") != kernel_source_sha(kernel_file):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: float) -> dict:
+    """Roofline of one labeling launch from its algorithmic bytes or ops.
+
+    bits    : dense bitpacked T (8 B per 64-cell word of every row) + packed
+              frame masks (W x 64 x 8 B) + L (1 B per pair)          -> HBM
+    sparse  : sparse layout (12 B per (row, word) entry + word pointers +
+              chunk table) + cell masks (W x 64 x 8 B) + label bits
+              (8 B per row)                                           -> HBM
+    mfma    : 2 N_t N_c N_p int8 multiply-adds                         -> MFMA
+    mfma_i8 : int8 T (1 B per cell of every row) + masks + L           -> HBM
+    """
+    W = info["n_words"]
+    t = kernel_ms * 1e-3
+    if kernel == "mfma":
+        ops = 2.0 * n_traj * W * 64 * n_props
+        return {"bound": "mfma", "achieved": ops / t / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": ops / t / 1e12 / INT8_PEAK_TOPS, "traffic": None, "kernel": "label_mfma",
+                "kernel_ms": kernel_ms, "algorithmic_ops": ops}
+    if kernel == "sparse":
+        alg, src, summary = info["sparse_bytes"] + W * 64 * 8 + n_traj * 8, "sparse.hip", "label_sparse_200k_512_64_traffic.json"
+    elif kernel == "mfma_i8":
+        alg, src, summary = n_traj * W * 64 + W * 64 * 8 + n_traj * n_props, "label_mfma.hip", None
+    else:
+        alg, src, summary = info["bits_bytes"] + W * 64 * 8 + n_traj * n_props, "label_bits.hip", "label_bits_200k_512_64_traffic.json"
+    achieved = alg / t / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profile(src, summary) if summary else None,
+            "kernel": "label_" + kernel, "kernel_ms": kernel_ms, "algorithmic_bytes": alg}
 
 
 def load_batch_abstractions(lbl, gen):
@@ -289,13 +321,12 @@ def main():
     value = pairs * args.steps / wall
     label_ms = prof["label_ms"] / max(1, prof["label_launches"])
     pack_ms = prof["pack_ms"] / max(1, prof["pack_launches"])
+    emit_ms = prof["emit_ms"] / max(1, prof["emit_launches"]) if prof["emit_launches"] else 0.0
     W = info["n_words"]
-    alg_bytes = info["bits_bytes"] + W * 64 * 8 + a.n_traj * n_props
-    achieved = alg_bytes / (label_ms * 1e-3) / 1e9
-    kernel_file = "label_bits.hip" if "bits" in plan else "label_mfma.hip"
-    traffic = traffic_from_profile(kernel_file, "label_bits_200k_512_64_traffic.json") if "bits" in plan else None
-    log(f"step {ms_per_step:.3f} ms, label kernel {label_ms:.3f} ms, pack {pack_ms:.3f} ms, "
-        f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}%)")
+    kernel = plan.split("-> ")[-1].split("(")[0]
+    roof = roofline(kernel, info, a.n_traj, n_props, label_ms)
+    log(f"step {ms_per_step:.3f} ms, label kernel {label_ms:.4f} ms, pack {pack_ms:.4f} ms, emit {emit_ms:.4f} ms, "
+        f"{roof['achieved']:.0f} {roof['unit']} ({100 * roof['frac']:.1f}%)")
 
     out = {
         "metric": METRIC,
@@ -318,11 +349,8 @@ def main():
                    "t_row_density": info["set_cells"] / (a.n_traj * a.grid.n_cells),
                    "t_nonzero_word_frac": info["nonzero_words"] / (a.n_traj * W),
                    "plan": plan, "frames": args.frames},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel_file.replace(".hip", ""), "kernel_ms": label_ms,
-                     "algorithmic_bytes": alg_bytes},
-        "stages_ms": {"pack_O": pack_ms, "label": label_ms},
+        "roofline": roof,
+        "stages_ms": {"pack_O": pack_ms, "label": label_ms, "emit_L": emit_ms},
     }
 
     if not args.no_pcie:
@@ -340,20 +368,19 @@ def main():
     if not args.no_sweep:
         sweep = []
         h8 = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+        info8 = lbl.abstraction_info(h8)
         for rho in (0.01, 0.10, 0.40):
             Ox = [torch.from_numpy(gen.make_frame(3, a.grid, n_props, frame=100 + f, rho=rho)).cuda()
                   for f in range(2)]
-            for name in ("bits", "mfma", "mfma_i8"):
+            for name in ("sparse", "bits", "mfma", "mfma_i8"):
                 kf = kernel_flag(lbl, name)
                 lbl.label_frame(h8, Ox[0], n_props, L, flags=kf, stream=stream)
                 w, pr = timed_steps(lbl, torch, h8, Ox, n_props, L, kf, args.sweep_steps, stream)
                 kms = pr["label_ms"] / max(1, pr["label_launches"])
-                t_bytes = info["bits_bytes"] if name != "mfma_i8" else a.n_traj * W * 64
-                ops = 2.0 * a.n_traj * W * 64 * n_props
-                sweep.append({"rho": rho, "kernel": name, "kernel_ms": kms,
-                              "pairs_per_s": pairs / (kms * 1e-3),
-                              "t_gbs": t_bytes / (kms * 1e-3) / 1e9,
-                              "dense_int8_tops": ops / (kms * 1e-3) / 1e12})
+                r = roofline(name, info8, a.n_traj, n_props, kms)
+                sweep.append({"rho": rho, "kernel": name, "kernel_ms": kms, "step_ms": 1000 * w / args.sweep_steps,
+                              "pairs_per_s": pairs / (kms * 1e-3), "roofline_bound": r["bound"],
+                              "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]})
                 log("sweep", sweep[-1])
         lbl.free_abstraction(h8)
         out["kernel_sweep"] = sweep

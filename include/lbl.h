@@ -69,11 +69,14 @@ typedef struct {
 /* ---- flags for lbl_load_abstraction* ---------------------------------- */
 #define LBL_LOAD_KEEP_INT8 0x1u    /* also keep an int8 copy of T (N_t x N_c bytes) */
 #define LBL_LOAD_INPUT_DEVICE 0x2u /* the input arrays are device pointers */
+#define LBL_LOAD_NO_SPARSE 0x4u    /* do not build the sparse word-major layout */
 
 /* ---- flags for lbl_label_frame / lbl_label_batch ---------------------- */
 #define LBL_HOST_PTRS 0x1u      /* O and L are host pointers; the call is synchronous */
 #define LBL_KERNEL_AUTO 0x00u   /* kernel and tile chosen by the autotuner cache */
-#define LBL_KERNEL_BITS 0x10u   /* bitpacked AND/OR wavefront kernel */
+#define LBL_KERNEL_BITS 0x10u   /* bitpacked AND/OR wavefront kernel (dense bitpacked T) */
+#define LBL_KERNEL_SPARSE 0x80u /* sparse word-major T, nibble tables per word
+                                   (needs the sparse layout, built by default) */
 #define LBL_KERNEL_MFMA 0x20u   /* int8 MFMA kernel, T expanded from its bitpacked copy */
 #define LBL_KERNEL_MFMA_I8 0x40u /* int8 MFMA kernel reading the int8 copy of T
                                    (needs LBL_LOAD_KEEP_INT8) */
@@ -120,6 +123,8 @@ typedef struct {
     uint64_t int8_bytes;     /* device bytes of the int8 T (0 if not kept) */
     uint64_t nonzero_words;  /* words of the bitpacked T holding at least one set cell */
     uint64_t set_cells;      /* distinct (trajectory, cell) pairs set in T */
+    uint64_t sparse_entries; /* (row, word) entries of the sparse layout (0 if not built) */
+    uint64_t sparse_bytes;   /* device bytes of the sparse layout */
 } lbl_abs_info;
 
 lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);
@@ -248,10 +253,12 @@ lbl_status lbl_serve_stop(lbl_server_t s);
 typedef struct {
     uint64_t pack_launches;   /* O packing kernels timed (lbl_label_frame) */
     uint64_t label_launches;  /* labeling kernels timed (lbl_label_frame) */
-    uint64_t batch_launches;  /* whole batches timed (lbl_label_batch: packing + labeling) */
+    uint64_t batch_launches;  /* whole batches timed (lbl_label_batch) */
+    uint64_t emit_launches;   /* label-bit to byte kernels timed (sparse kernel only) */
     double pack_ms;           /* summed durations */
     double label_ms;
     double batch_ms;
+    double emit_ms;
 } lbl_profile;
 
 lbl_status lbl_profile_enable(int on);

@@ -6,6 +6,7 @@
 #include <unordered_map>
 
 #include "lbl_internal.h"
+#include "sparse.h"
 #include "tune.h"
 
 namespace lbl {
@@ -135,6 +136,9 @@ static void abs_release(lbl_abs *a)
     (void)hipFree(a->T_i8);
     (void)hipFree(a->d_tile_word);
     (void)hipFree(a->d_word_cell);
+    (void)hipFree(a->sp_seg);
+    (void)hipFree(a->sp_row);
+    (void)hipFree(a->sp_val);
     (void)hipSetDevice(cur);
 }
 
@@ -165,6 +169,10 @@ static lbl_status abs_finish(lbl_abs *a, uint32_t flags)
         LBL_HIP_TRY(launch_expand_i8(a->T_i8, a->T_bits, a->row_stride, a->n_traj, a->n_words, nullptr));
     }
     LBL_HIP_TRY(hipDeviceSynchronize());
+    if (!(flags & LBL_LOAD_NO_SPARSE)) {
+        lbl_status st = build_sparse(a);
+        if (st != LBL_OK) return st;
+    }
     return LBL_OK;
 }
 
@@ -211,7 +219,7 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
     *out = nullptr;
     LBL_REQUIRE(row_ptr != nullptr, "row_ptr is null");
     LBL_REQUIRE(n_traj > 0, "n_traj must be positive");
-    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE)) == 0, "unknown load flag");
+    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE | LBL_LOAD_NO_SPARSE)) == 0, "unknown load flag");
     const bool dev_in = flags & LBL_LOAD_INPUT_DEVICE;
 
     // row pointers on the host for validation and chunking
@@ -288,7 +296,7 @@ lbl_status lbl_load_abstraction_dense(const lbl_grid *grid, uint64_t n_traj, con
     *out = nullptr;
     LBL_REQUIRE(T != nullptr, "T is null");
     LBL_REQUIRE(n_traj > 0, "n_traj must be positive");
-    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE)) == 0, "unknown load flag");
+    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE | LBL_LOAD_NO_SPARSE)) == 0, "unknown load flag");
     std::unique_ptr<lbl_abs> tmp;
     st = abs_alloc(grid, n_traj, tmp);
     std::unique_ptr<lbl_abs, AbsDeleter> a(tmp.release());
@@ -321,7 +329,7 @@ lbl_status lbl_free_abstraction(lbl_abs_t a)
 {
     clear_error();
     if (!a) return LBL_OK;
-    tune_forget(a);
+    batch_forget(a);
     abs_release(a);
     delete a;
     return LBL_OK;
@@ -340,6 +348,10 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
     out->int8_bytes = a->T_i8 ? a->n_traj * a->n_words * 64ull : 0;
     out->nonzero_words = a->nonzero_words;
     out->set_cells = a->set_cells;
+    out->sparse_entries = a->sp_seg ? a->sp_nnz : 0;
+    out->sparse_bytes = a->sp_seg ? a->sp_nnz * (sizeof(uint16_t) + sizeof(uint64_t)) +
+                                        (a->sp_geom.n_rb * (uint64_t)a->n_words + 1) * sizeof(uint64_t)
+                                  : 0;
     return LBL_OK;
 }
 
@@ -353,10 +365,12 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
     LBL_REQUIRE((flags & ~(LBL_HOST_PTRS | LBL_KERNEL_MASK)) == 0, "unknown flag");
     const uint32_t kflag = flags & LBL_KERNEL_MASK;
     LBL_REQUIRE(kflag == LBL_KERNEL_AUTO || kflag == LBL_KERNEL_BITS || kflag == LBL_KERNEL_MFMA ||
-                    kflag == LBL_KERNEL_MFMA_I8,
+                    kflag == LBL_KERNEL_MFMA_I8 || kflag == LBL_KERNEL_SPARSE,
                 "unknown kernel flag");
     LBL_REQUIRE(kflag != LBL_KERNEL_MFMA_I8 || a->T_i8 != nullptr,
                 "LBL_KERNEL_MFMA_I8 needs an abstraction loaded with LBL_LOAD_KEEP_INT8");
+    LBL_REQUIRE(kflag != LBL_KERNEL_SPARSE || a->sp_seg != nullptr,
+                "LBL_KERNEL_SPARSE needs the sparse layout (loaded without LBL_LOAD_NO_SPARSE, fewer than 2^32 rows)");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     int cur = 0;
     LBL_HIP_TRY(hipGetDevice(&cur));

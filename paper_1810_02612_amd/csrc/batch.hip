@@ -378,6 +378,21 @@ lbl_status build_entry(GraphEntry *e)
 
 BatchTile batch_tile_for(const std::string &key) { return tuned_tile(key); }
 
+void batch_forget(const lbl_abs *a)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        bool uses = false;
+        for (const JobRef &j : (*it)->jobs) uses = uses || j.a == a;
+        if (uses) {
+            destroy_entry(it->get());
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 void set_batch_tile(const std::string &key, const BatchTile &t)
 {
     std::lock_guard<std::mutex> lk(g_tile_mu);

@@ -48,6 +48,14 @@ struct CellOrder {
 
 uint32_t morton2(uint32_t x, uint32_t y);  // x bits at odd positions
 
+// Geometry of the sparse tiled layout: tiles are (row block, word range).
+struct SparseGeom {
+    uint32_t n_rb = 0;      // row blocks
+    uint32_t n_wr = 0;      // word ranges
+    uint32_t wr_words = 0;  // words per word range
+    uint64_t n_tiles() const { return (uint64_t)n_rb * n_wr; }
+};
+
 }  // namespace lbl
 
 // Abstraction: device-resident T in bitpacked (and optionally int8) layout.
@@ -66,6 +74,12 @@ struct lbl_abs {
     uint64_t nonzero_words = 0;
     uint64_t set_cells = 0;
     lbl::CellOrder order;
+    // sparse tiled layout (null when not built)
+    uint64_t *sp_seg = nullptr;  // [n_rb * n_words + 1] entry offsets of segments (rb, w)
+    uint16_t *sp_row = nullptr;  // [sp_nnz] row within the row block
+    uint64_t *sp_val = nullptr;  // [sp_nnz] word value
+    uint64_t sp_nnz = 0;
+    lbl::SparseGeom sp_geom;
 };
 
 namespace lbl {
@@ -76,7 +90,7 @@ lbl_status workspace(hipStream_t s, size_t bytes, void **out);
 // ---------------------------------------------------------------- kernels
 
 // Kernel choices (runtime representation of LBL_KERNEL_*).
-enum class Kernel : int { Bits = 0, Mfma = 1, MfmaI8 = 2 };
+enum class Kernel : int { Bits = 0, Mfma = 1, MfmaI8 = 2, Sparse = 3 };
 
 struct BitsTile {
     int unroll = 8;          // 16-byte loads per lane in flight per step

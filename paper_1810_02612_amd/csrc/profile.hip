@@ -9,15 +9,15 @@ namespace {
 
 struct Span {
     hipEvent_t a, b;
-    int kind;  // 0 pack, 1 label, 2 batch
+    int kind;  // 0 pack, 1 label, 2 batch, 3 emit
 };
 
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Span> g_pending;
 std::vector<hipEvent_t> g_free;
-uint64_t g_n[3] = {0, 0, 0};
-double g_ms[3] = {0.0, 0.0, 0.0};
+uint64_t g_n[4] = {0, 0, 0, 0};
+double g_ms[4] = {0.0, 0.0, 0.0, 0.0};
 
 hipEvent_t take()
 {
@@ -98,8 +98,10 @@ lbl_status lbl_profile_enable(int on)
     std::lock_guard<std::mutex> lk(g_mu);
     LBL_HIP_TRY(drain(true));
     g_on = on != 0;
-    g_n[0] = g_n[1] = g_n[2] = 0;
-    g_ms[0] = g_ms[1] = g_ms[2] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        g_n[k] = 0;
+        g_ms[k] = 0.0;
+    }
     return LBL_OK;
 }
 
@@ -112,9 +114,11 @@ lbl_status lbl_profile_read(lbl_profile *out)
     out->pack_launches = g_n[0];
     out->label_launches = g_n[1];
     out->batch_launches = g_n[2];
+    out->emit_launches = g_n[3];
     out->pack_ms = g_ms[0];
     out->label_ms = g_ms[1];
     out->batch_ms = g_ms[2];
+    out->emit_ms = g_ms[3];
     return LBL_OK;
 }
 

@@ -22,7 +22,8 @@ size_t plan_ow_bytes(const lbl_abs *a, uint32_t n_props, const Plan &p);
 // Pack O into Ow and run the plan's label kernel, writing L (device pointers).
 lbl_status run_plan(const lbl_abs *a, const Plan &p, const uint8_t *O, uint32_t n_props, void *Ow, uint8_t *L,
                     hipStream_t s);
-void tune_forget(const lbl_abs *a);
+// Drop cached batch graphs that reference a (before a is freed).
+void batch_forget(const lbl_abs *a);
 std::string plan_name(const Plan &p);
 
 hipError_t launch_label_mfma(const lbl_abs *a, const uint64_t *Ow, uint32_t n_props, uint8_t *L,

@@ -14,6 +14,7 @@
 #include <sstream>
 
 #include "profile.h"
+#include "sparse.h"
 #include "tune.h"
 
 namespace lbl {
@@ -46,6 +47,7 @@ const char *kernel_name(Kernel k)
     case Kernel::Bits: return "bits";
     case Kernel::Mfma: return "mfma";
     case Kernel::MfmaI8: return "mfma_i8";
+    case Kernel::Sparse: return "sparse";
     }
     return "?";
 }
@@ -55,8 +57,23 @@ bool kernel_from_name(const std::string &s, Kernel *k)
     if (s == "bits") *k = Kernel::Bits;
     else if (s == "mfma") *k = Kernel::Mfma;
     else if (s == "mfma_i8") *k = Kernel::MfmaI8;
+    else if (s == "sparse") *k = Kernel::Sparse;
     else return false;
     return true;
+}
+
+// The plan used when nothing was tuned: the sparse kernel where the layout
+// exists, else the bitpacked kernel.
+Plan default_plan(const lbl_abs *a)
+{
+    Plan p;
+    p.kernel = a->sp_seg ? Kernel::Sparse : Kernel::Bits;
+    return p;
+}
+
+bool plan_usable(const lbl_abs *a, const Plan &p)
+{
+    return !(p.kernel == Kernel::MfmaI8 && !a->T_i8) && !(p.kernel == Kernel::Sparse && !a->sp_seg);
 }
 
 // Synthetic frame: every (cell, proposition) byte is 1 with probability
@@ -81,6 +98,8 @@ std::string plan_name(const Plan &p)
     char buf[96];
     if (p.kernel == Kernel::Bits)
         snprintf(buf, sizeof(buf), "bits(unroll=%d,waves=%d)", p.bits.unroll, p.bits.waves_per_block);
+    else if (p.kernel == Kernel::Sparse)
+        snprintf(buf, sizeof(buf), "sparse(rows=%u,waves=%u,words=%u)", kRowBlock, kTileWaves, kWordGroup);
     else
         snprintf(buf, sizeof(buf), "%s(m_tiles=%d,waves=%d)", kernel_name(p.kernel), p.mfma.m_tiles,
                  p.mfma.waves_per_block);
@@ -93,21 +112,29 @@ Plan choose(const lbl_abs *a, uint32_t n_props, uint32_t kflag)
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(shape_key(a, n_props));
     if (kflag == LBL_KERNEL_AUTO) {
-        if (it != g_cache.end()) p = it->second.plan;
-        if (p.kernel == Kernel::MfmaI8 && !a->T_i8) p = Plan{};
+        p = it != g_cache.end() ? it->second.plan : default_plan(a);
+        if (!plan_usable(a, p)) p = default_plan(a);
         return p;
     }
-    p.kernel = kflag == LBL_KERNEL_BITS ? Kernel::Bits : kflag == LBL_KERNEL_MFMA ? Kernel::Mfma : Kernel::MfmaI8;
+    p.kernel = kflag == LBL_KERNEL_BITS     ? Kernel::Bits
+               : kflag == LBL_KERNEL_MFMA   ? Kernel::Mfma
+               : kflag == LBL_KERNEL_SPARSE ? Kernel::Sparse
+                                            : Kernel::MfmaI8;
     // keep tuned tile shapes when the cached winner is the same kernel
     if (it != g_cache.end() && it->second.plan.kernel == p.kernel) p = it->second.plan;
     return p;
 }
 
-size_t plan_ow_bytes(const lbl_abs *a, uint32_t, const Plan &) { return (size_t)a->n_words * 64 * sizeof(uint64_t); }
+size_t plan_ow_bytes(const lbl_abs *a, uint32_t, const Plan &p)
+{
+    if (p.kernel == Kernel::Sparse) return swm_workspace_bytes(a);
+    return (size_t)a->n_words * 64 * sizeof(uint64_t);
+}
 
 lbl_status run_plan(const lbl_abs *a, const Plan &p, const uint8_t *O, uint32_t n_props, void *Ow, uint8_t *L,
                     hipStream_t s)
 {
+    if (p.kernel == Kernel::Sparse) return run_swm(a, O, n_props, Ow, L, s);
     uint64_t *ow = static_cast<uint64_t *>(Ow);
     if (p.kernel != Kernel::Bits) {
         lbl_status st = mfma_layout_selftest();
@@ -123,12 +150,12 @@ lbl_status run_plan(const lbl_abs *a, const Plan &p, const uint8_t *O, uint32_t 
     case Kernel::MfmaI8:
         LBL_HIP_TRY(launch_label_mfma(a, ow, n_props, L, p.mfma, p.kernel == Kernel::MfmaI8, s));
         break;
+    case Kernel::Sparse: break;  // handled above
     }
     span_end(span, s, 1);
     return LBL_OK;
 }
 
-void tune_forget(const lbl_abs *) {}
 
 }  // namespace lbl
 
@@ -145,13 +172,16 @@ lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const size_t o_bytes = (size_t)a->n_cells * n_props;
     const size_t l_bytes = (size_t)a->n_traj * n_props;
-    const size_t ow_bytes = (size_t)a->n_words * 64 * sizeof(uint64_t);
+    // workspace large enough for every candidate plan
+    size_t ws_bytes = (size_t)a->n_words * 64 * sizeof(uint64_t);
+    if (a->sp_seg) ws_bytes = std::max(ws_bytes, swm_workspace_bytes(a));
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     uint8_t *buf = nullptr;
-    LBL_HIP_TRY(hipMalloc(&buf, o_bytes + l_bytes + ow_bytes + 1024));
+    LBL_HIP_TRY(hipMalloc(&buf, up(ws_bytes) + up(l_bytes) + up(o_bytes)));
     std::unique_ptr<uint8_t, decltype(&hipFree)> guard(buf, &hipFree);
     uint64_t *Ow = reinterpret_cast<uint64_t *>(buf);
-    uint8_t *L = buf + ((ow_bytes + 255) & ~size_t(255));
-    uint8_t *O = L + ((l_bytes + 255) & ~size_t(255));
+    uint8_t *L = buf + up(ws_bytes);
+    uint8_t *O = L + up(l_bytes);
     if (O_sample) {
         O = const_cast<uint8_t *>(O_sample);
     } else {
@@ -160,6 +190,11 @@ lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint
         LBL_HIP_TRY(hipGetLastError());
     }
     std::vector<Plan> cands;
+    if (a->sp_seg) {
+        Plan p;
+        p.kernel = Kernel::Sparse;
+        cands.push_back(p);
+    }
     for (int u : {2, 4, 8, 16})
         for (int w : {2, 4, 8}) {
             Plan p;

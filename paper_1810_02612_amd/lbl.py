@@ -23,11 +23,13 @@ STATUS_NAMES = {0: "LBL_OK", 1: "LBL_EINVAL", 2: "LBL_ENOMEM", 3: "LBL_EDEVICE",
 
 LOAD_KEEP_INT8 = 0x1
 LOAD_INPUT_DEVICE = 0x2
+LOAD_NO_SPARSE = 0x4
 HOST_PTRS = 0x1
 KERNEL_AUTO = 0x00
 KERNEL_BITS = 0x10
 KERNEL_MFMA = 0x20
 KERNEL_MFMA_I8 = 0x40
+KERNEL_SPARSE = 0x80
 BATCH_MAX_PROPS = 1024
 
 EXPORTS = (
@@ -52,7 +54,8 @@ class Grid(ctypes.Structure):
 class AbsInfo(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_uint64), ("nx", ctypes.c_uint32), ("ny", ctypes.c_uint32),
                 ("n_words", ctypes.c_uint32), ("row_stride", ctypes.c_uint32), ("bits_bytes", ctypes.c_uint64),
-                ("int8_bytes", ctypes.c_uint64), ("nonzero_words", ctypes.c_uint64), ("set_cells", ctypes.c_uint64)]
+                ("int8_bytes", ctypes.c_uint64), ("nonzero_words", ctypes.c_uint64), ("set_cells", ctypes.c_uint64),
+                ("sparse_entries", ctypes.c_uint64), ("sparse_bytes", ctypes.c_uint64)]
 
 
 class Job(ctypes.Structure):
@@ -62,8 +65,9 @@ class Job(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("pack_launches", ctypes.c_uint64), ("label_launches", ctypes.c_uint64),
-                ("batch_launches", ctypes.c_uint64), ("pack_ms", ctypes.c_double), ("label_ms", ctypes.c_double),
-                ("batch_ms", ctypes.c_double)]
+                ("batch_launches", ctypes.c_uint64), ("emit_launches", ctypes.c_uint64),
+                ("pack_ms", ctypes.c_double), ("label_ms", ctypes.c_double),
+                ("batch_ms", ctypes.c_double), ("emit_ms", ctypes.c_double)]
 
 
 class ServeCfg(ctypes.Structure):

@@ -17,7 +17,8 @@ from paper_1810_02612_amd import lbl  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = {"bits": lbl.KERNEL_BITS, "mfma": lbl.KERNEL_MFMA, "mfma_i8": lbl.KERNEL_MFMA_I8}
+KERNELS = {"sparse": lbl.KERNEL_SPARSE, "bits": lbl.KERNEL_BITS, "mfma": lbl.KERNEL_MFMA,
+           "mfma_i8": lbl.KERNEL_MFMA_I8, "auto": lbl.KERNEL_AUTO}
 THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -162,7 +163,7 @@ def test_cfg3_full_size_sampled_rows():
         rows[-1] = a.n_traj - 1
         for rho in (0.01, 0.4):
             O = gen.make_frame(3, a.grid, 64, frame=1, rho=rho)
-            for name in ("bits", "mfma"):
+            for name in ("sparse", "bits", "mfma"):
                 say(f"cfg3 full rho={rho} kernel {name}")
                 L = label(h, O, a.n_traj, KERNELS[name])
                 assert_same(L[rows.astype(np.int64)], expect(a, O, rows), f"cfg3-full/{name}/rho{rho}")
@@ -230,7 +231,8 @@ def test_dense_and_device_csr_loads_agree(cfg1):
                               torch.from_numpy(a.col_idx.astype(np.int32)).cuda(), lbl.LOAD_INPUT_DEVICE)
     try:
         for h in (h1, h2, h3):
-            assert_same(label(h, O, a.n_traj, lbl.KERNEL_BITS), want, "alt-load")
+            for k in (lbl.KERNEL_BITS, lbl.KERNEL_SPARSE):
+                assert_same(label(h, O, a.n_traj, k), want, "alt-load")
     finally:
         for h in (h1, h2, h3):
             lbl.free_abstraction(h)
@@ -273,7 +275,8 @@ def test_two_streams_same_abstraction(cfg1):
         say("two streams")
         for rep in range(5):
             for i in range(2):
-                lbl.label_frame(h, Od[i], 8, Ld[i], flags=lbl.KERNEL_BITS, stream=streams[i])
+                lbl.label_frame(h, Od[i], 8, Ld[i], flags=(lbl.KERNEL_BITS, lbl.KERNEL_SPARSE)[rep % 2],
+                                stream=streams[i])
         torch.cuda.synchronize()
         for i in range(2):
             assert_same(Ld[i].cpu().numpy(), wants[i], f"stream{i}")
