@@ -19,13 +19,34 @@ struct LaneDesc {
 struct GroupDesc {
     const uint64_t *T;
     const uint32_t *word_cell;
-    uint64_t *Ow;             // [n_words][G64][64] packed masks
+    uint64_t *Ow;             // [n_words][G64][64] packed masks: bitpacked plans index the
+                              // last axis by column (64 cells per mask), sparse plans by
+                              // cell (64 columns per mask)
     const LaneDesc *lanes;    // [G64][64]
     uint64_t n_traj;
     uint32_t row_stride;
     uint32_t n_words;
     uint32_t G64;
-    uint32_t pad;
+    uint32_t n_rb;            // sparse: row blocks
+    // sparse tiled layout of T and this pass's partial labels
+    const uint64_t *sp_seg;
+    const uint16_t *sp_row;
+    const uint64_t *sp_val;
+    uint64_t max_entry;
+    uint64_t *P;              // [G64][n_wr][n_rb * kRowBlock]
+    uint32_t n_wr;
+    uint32_t wr_words;
+};
+
+// Sparse plans: one workgroup per (group, tile, lane group).
+struct TileItem {
+    uint32_t group, rb, wr, gi;
+};
+
+// Sparse plans: one wavefront per (group, lane group, 64-row chunk range).
+struct CombineItem {
+    uint32_t group, gi;
+    uint64_t row0, row1;
 };
 
 struct WorkItem {
@@ -60,6 +81,12 @@ struct BatchPlan {
     BatchTile tile;
     uint64_t pairs = 0;             // labeled (trajectory, proposition) pairs
     std::string shape_key;
+    // sparse plans (every abstraction of the batch has the sparse layout)
+    bool sparse = false;
+    std::vector<size_t> p_off;      // byte offset of each group's partials in the P region
+    size_t p_bytes = 0;
+    std::vector<TileItem> tiles;
+    std::vector<CombineItem> combines;
 
     bool finalized = false;         // tile set and items made
 
@@ -87,7 +114,15 @@ struct BatchBuffers {
     uint64_t *d_pack_prefix = nullptr;
     uint32_t *d_counter = nullptr;
     uint64_t *d_ow = nullptr;
+    TileItem *d_tiles = nullptr;
+    CombineItem *d_combines = nullptr;
+    uint64_t *d_p = nullptr;
 };
+
+// Sparse batch kernels (defined with the sparse layout's kernels).
+hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_combine_batch(const GroupDesc *d_groups, const CombineItem *d_items, uint32_t n_items,
+                                hipStream_t s);
 
 // Lay the finalized plan out in `base` (capacity bytes of device memory) and
 // fill `host_image` with the bytes to copy to base (tables; masks excluded).

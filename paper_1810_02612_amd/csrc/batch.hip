@@ -16,6 +16,7 @@
 
 #include "batch.h"
 #include "profile.h"
+#include "sparse.h"
 
 namespace lbl {
 
@@ -34,7 +35,11 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int src)
 __global__ void k_zero(uint32_t *counter) { *counter = 0u; }
 
 // One wavefront per (group, word, lane group): lane l packs the 64 cells of
-// the word for the proposition column that lane (gi, l) stands for.
+// the word for the proposition column that lane (gi, l) stands for.  With
+// PER_CELL the 64 x 64 bit block is transposed across the wavefront (64
+// ballots) so that lane b stores the mask of columns met by cell b, the
+// layout the sparse kernels read.
+template <bool PER_CELL>
 __global__ void __launch_bounds__(256)
 k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
              uint64_t n_units)
@@ -53,6 +58,15 @@ k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ 
             const uint32_t *wc = g.word_cell + (uint64_t)w * 64;
 #pragma unroll 16
             for (uint32_t b = 0; b < 64; ++b) m |= (uint64_t)(d.O[(uint64_t)wc[b] * d.n_props] != 0) << b;
+        }
+        if (PER_CELL) {
+            uint64_t t = 0;
+#pragma unroll
+            for (uint32_t b = 0; b < 64; ++b) {
+                const uint64_t col = __ballot((m >> b) & 1ull);  // bit l: column l meets cell b
+                t = lane == b ? col : t;
+            }
+            m = t;
         }
         g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
     }
@@ -155,16 +169,31 @@ int device_cu_count()
 size_t batch_table_bytes(const BatchPlan &p)
 {
     return up256(p.groups.size() * sizeof(GroupDesc)) + up256(p.items.size() * sizeof(WorkItem)) +
-           up256(p.lanes.size() * sizeof(LaneDesc)) + up256((p.groups.size() + 1) * sizeof(uint64_t)) + 256;
+           up256(p.lanes.size() * sizeof(LaneDesc)) + up256((p.groups.size() + 1) * sizeof(uint64_t)) + 256 +
+           up256(p.tiles.size() * sizeof(TileItem)) + up256(p.combines.size() * sizeof(CombineItem));
 }
 
-size_t BatchPlan::device_bytes() const { return batch_table_bytes(*this) + ow_bytes; }
+size_t BatchPlan::device_bytes() const { return batch_table_bytes(*this) + ow_bytes + p_bytes; }
+
+// Word ranges per tile for a sparse pass with G lane groups: about
+// kTilesPerPass tiles per pass, at least kTileWaves words per tile, and at
+// most 8 ranges so that the partials (G x ranges x row blocks of kRowBlock
+// rows) stay a small multiple of the labels themselves.
+static uint32_t batch_word_ranges(const lbl_abs *a, uint32_t G)
+{
+    const uint32_t kTilesPerPass = 512, kMaxRanges = 8;
+    const uint64_t per = (uint64_t)a->sp_geom.n_rb * G;
+    uint32_t n_wr = (uint32_t)std::max<uint64_t>(1, (kTilesPerPass + per - 1) / per);
+    n_wr = std::min(n_wr, kMaxRanges);
+    return std::min<uint32_t>(n_wr, std::max<uint32_t>(1, a->n_words / (kTileWaves * kWordGroup)));
+}
 
 lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *out)
 {
     LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
     std::vector<lbl_abs *> order;
     std::map<lbl_abs *, std::vector<size_t>> by_abs;
+    bool all_sparse = true;
     for (size_t j = 0; j < n_jobs; ++j) {
         const JobRef &r = jobs[j];
         LBL_REQUIRE(r.a != nullptr, "job " + std::to_string(j) + ": abstraction is null");
@@ -173,9 +202,11 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
         LBL_REQUIRE(device < 0 || r.a->device == device, "job " + std::to_string(j) + ": abstraction lives on another device");
         if (!by_abs.count(r.a)) order.push_back(r.a);
         by_abs[r.a].push_back(j);
+        all_sparse = all_sparse && r.a->sp_seg != nullptr;
     }
     BatchPlan &p = *out;
     p = BatchPlan{};
+    p.sparse = all_sparse;
     std::vector<std::string> keys;
     for (lbl_abs *a : order) {
         const auto &js = by_abs[a];
@@ -192,6 +223,18 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             g.row_stride = a->row_stride;
             g.n_words = a->n_words;
             g.G64 = (P + 63) / 64;
+            if (p.sparse) {
+                g.n_rb = a->sp_geom.n_rb;
+                g.sp_seg = a->sp_seg;
+                g.sp_row = a->sp_row;
+                g.sp_val = a->sp_val;
+                g.max_entry = std::max<uint64_t>(a->sp_nnz, 1) - 1;
+                g.n_wr = batch_word_ranges(a, g.G64);
+                g.wr_words = (a->n_words + g.n_wr - 1) / g.n_wr;
+                g.n_wr = (a->n_words + g.wr_words - 1) / g.wr_words;
+                p.p_off.push_back(p.p_bytes);
+                p.p_bytes += up256((size_t)g.G64 * g.n_wr * g.n_rb * kRowBlock * sizeof(uint64_t));
+            }
             p.lane_off.push_back(p.lanes.size());
             p.lanes.resize(p.lanes.size() + (size_t)g.G64 * 64, LaneDesc{nullptr, nullptr, 0, 0});
             size_t q = p.lane_off.back();
@@ -211,6 +254,7 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
     }
     std::sort(keys.begin(), keys.end());
     for (auto &s : keys) p.shape_key += s + ";";
+    if (p.sparse) p.shape_key = "sparse;" + p.shape_key;
     return LBL_OK;
 }
 
@@ -218,14 +262,36 @@ void plan_finalize(BatchPlan &p, const BatchTile &tile)
 {
     p.tile = tile;
     p.items.clear();
+    p.tiles.clear();
+    p.combines.clear();
     std::vector<uint32_t> idx(p.groups.size());
     for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    auto cost = [&](uint32_t g) { return (double)p.groups[g].n_words * (4.0 + p.groups[g].G64); };
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
-    const uint64_t R = (uint64_t)std::max(1, p.tile.rows_per_item);
-    for (uint32_t g : idx)
-        for (uint64_t r0 = 0; r0 < p.groups[g].n_traj; r0 += R)
-            p.items.push_back(WorkItem{g, 0, r0, std::min(r0 + R, p.groups[g].n_traj)});
+    if (p.sparse) {
+        // tiles of the passes with the most entries per tile first
+        auto cost = [&](uint32_t g) {
+            const GroupDesc &d = p.groups[g];
+            return (double)(d.max_entry + 1) / ((double)d.n_rb * d.n_wr);
+        };
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
+        for (uint32_t g : idx) {
+            const GroupDesc &d = p.groups[g];
+            for (uint32_t rb = 0; rb < d.n_rb; ++rb)
+                for (uint32_t wr = 0; wr < d.n_wr; ++wr)
+                    for (uint32_t gi = 0; gi < d.G64; ++gi) p.tiles.push_back(TileItem{g, rb, wr, gi});
+        }
+        const uint64_t R = 512;  // rows per combine item (a multiple of 64)
+        for (uint32_t g = 0; g < p.groups.size(); ++g)
+            for (uint32_t gi = 0; gi < p.groups[g].G64; ++gi)
+                for (uint64_t r0 = 0; r0 < p.groups[g].n_traj; r0 += R)
+                    p.combines.push_back(CombineItem{g, gi, r0, std::min(r0 + R, p.groups[g].n_traj)});
+    } else {
+        auto cost = [&](uint32_t g) { return (double)p.groups[g].n_words * (4.0 + p.groups[g].G64); };
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
+        const uint64_t R = (uint64_t)std::max(1, p.tile.rows_per_item);
+        for (uint32_t g : idx)
+            for (uint64_t r0 = 0; r0 < p.groups[g].n_traj; r0 += R)
+                p.items.push_back(WorkItem{g, 0, r0, std::min(r0 + R, p.groups[g].n_traj)});
+    }
     p.finalized = true;
 }
 
@@ -243,42 +309,61 @@ lbl_status bind_batch(const BatchPlan &p, uint8_t *base, size_t capacity, BatchB
     off += up256((p.groups.size() + 1) * sizeof(uint64_t));
     const size_t o_counter = off;
     off += 256;
+    const size_t o_tiles = off;
+    off += up256(p.tiles.size() * sizeof(TileItem));
+    const size_t o_combines = off;
+    off += up256(p.combines.size() * sizeof(CombineItem));
     const size_t o_ow = off;
-    if (off + p.ow_bytes > capacity || off + p.ow_bytes != p.device_bytes()) {
-        set_error("batch layout needs " + std::to_string(off + p.ow_bytes) + " bytes, buffer holds " +
-                  std::to_string(capacity));
+    const size_t o_p = o_ow + p.ow_bytes;
+    const size_t total = o_p + p.p_bytes;
+    if (total > capacity || total != p.device_bytes()) {
+        set_error("batch layout needs " + std::to_string(total) + " bytes, buffer holds " + std::to_string(capacity));
         return LBL_ENOMEM;
     }
     b->base = base;
-    b->bytes = off + p.ow_bytes;
+    b->bytes = total;
     b->d_groups = reinterpret_cast<GroupDesc *>(base + o_groups);
     b->d_items = reinterpret_cast<WorkItem *>(base + o_items);
     b->d_lanes = reinterpret_cast<LaneDesc *>(base + o_lanes);
     b->d_pack_prefix = reinterpret_cast<uint64_t *>(base + o_prefix);
     b->d_counter = reinterpret_cast<uint32_t *>(base + o_counter);
+    b->d_tiles = reinterpret_cast<TileItem *>(base + o_tiles);
+    b->d_combines = reinterpret_cast<CombineItem *>(base + o_combines);
     b->d_ow = reinterpret_cast<uint64_t *>(base + o_ow);
+    b->d_p = reinterpret_cast<uint64_t *>(base + o_p);
     img->assign(o_ow, 0);
     std::vector<GroupDesc> gs = p.groups;
     std::vector<uint64_t> prefix(p.groups.size() + 1, 0);
     for (size_t g = 0; g < gs.size(); ++g) {
         gs[g].Ow = reinterpret_cast<uint64_t *>(base + o_ow + p.ow_off[g]);
         gs[g].lanes = b->d_lanes + p.lane_off[g];
+        if (p.sparse) gs[g].P = reinterpret_cast<uint64_t *>(base + o_p + p.p_off[g]);
         prefix[g + 1] = prefix[g] + (uint64_t)gs[g].n_words * gs[g].G64;
     }
     memcpy(img->data() + o_groups, gs.data(), gs.size() * sizeof(GroupDesc));
     memcpy(img->data() + o_items, p.items.data(), p.items.size() * sizeof(WorkItem));
     memcpy(img->data() + o_lanes, p.lanes.data(), p.lanes.size() * sizeof(LaneDesc));
     memcpy(img->data() + o_prefix, prefix.data(), prefix.size() * sizeof(uint64_t));
+    memcpy(img->data() + o_tiles, p.tiles.data(), p.tiles.size() * sizeof(TileItem));
+    memcpy(img->data() + o_combines, p.combines.data(), p.combines.size() * sizeof(CombineItem));
     return LBL_OK;
 }
 
 lbl_status enqueue_batch(const BatchPlan &p, const BatchBuffers &b, hipStream_t s)
 {
     LBL_REQUIRE(p.finalized && b.base != nullptr, "batch enqueued before it was bound");
+    const uint64_t pack_blocks = std::max<uint64_t>(1, std::min<uint64_t>((p.pack_units + 3) / 4, 1u << 16));
+    if (p.sparse) {
+        hipLaunchKernelGGL(k_pack_batch<true>, dim3((unsigned)pack_blocks), dim3(256), 0, s, b.d_groups,
+                           b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units);
+        LBL_HIP_TRY(hipGetLastError());
+        LBL_HIP_TRY(launch_tiles_batch(b.d_groups, b.d_tiles, (uint32_t)p.tiles.size(), s));
+        LBL_HIP_TRY(launch_combine_batch(b.d_groups, b.d_combines, (uint32_t)p.combines.size(), s));
+        return LBL_OK;
+    }
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, b.d_counter);
     LBL_HIP_TRY(hipGetLastError());
-    const uint64_t pack_blocks = std::min<uint64_t>((p.pack_units + 3) / 4, 1u << 16);
-    hipLaunchKernelGGL(k_pack_batch, dim3((unsigned)std::max<uint64_t>(pack_blocks, 1)), dim3(256), 0, s, b.d_groups,
+    hipLaunchKernelGGL(k_pack_batch<false>, dim3((unsigned)pack_blocks), dim3(256), 0, s, b.d_groups,
                        b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units);
     LBL_HIP_TRY(hipGetLastError());
     const int wpb = p.tile.waves_per_block;

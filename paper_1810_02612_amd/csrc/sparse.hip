@@ -28,6 +28,7 @@
 // nor the split into tiles changes the result.  No global atomics are used.
 #include <algorithm>
 
+#include "batch.h"
 #include "profile.h"
 #include "sparse.h"
 
@@ -169,20 +170,18 @@ k_pack_cells(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__
 // Oc + w * oc_word_stride holds the 64 cell masks of word w.  Writes the
 // tile's partial labels to P[wr * p_stride + row] for its rows.
 template <int WAVES, int GROUP>
-__global__ void __launch_bounds__(64 * WAVES)
-k_label_tiles(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Oc, uint64_t oc_word_stride,
-              uint32_t n_words, uint32_t n_wr, uint32_t wr_words, uint64_t n_traj, uint64_t max_entry,
-              uint64_t *__restrict__ P, uint64_t p_stride)
+__device__ __forceinline__ void tile_body(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_row,
+                                          const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Oc,
+                                          uint64_t oc_word_stride, uint32_t n_words, uint32_t rb, uint32_t wr,
+                                          uint32_t wr_words, uint64_t n_traj, uint64_t max_entry,
+                                          uint64_t *__restrict__ P, uint64_t p_stride, uint64_t *lds)
 {
-    extern __shared__ uint64_t lds[];
     const uint32_t lane = threadIdx.x & 63;
     // uniform across the wavefront: segment bounds become scalar loads and
     // the per-group branches scalar branches
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t *acc = lds;                                      // kRowBlock accumulators
     uint64_t *tab = lds + kRowBlock + wave * (GROUP * 256);   // this wavefront's tables
-    const uint32_t rb = blockIdx.x / n_wr, wr = blockIdx.x % n_wr;
     for (uint32_t i = threadIdx.x; i < kRowBlock; i += blockDim.x) acc[i] = 0ull;
     __syncthreads();
     const uint32_t w_lo = wr * wr_words, w_hi = min(w_lo + wr_words, n_words);
@@ -279,6 +278,62 @@ k_label_tiles(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_
     for (uint32_t i = threadIdx.x; i < kRowBlock && row0 + i < n_traj; i += blockDim.x) Pw[i] = acc[i];
 }
 
+// One workgroup per tile of a single frame: tile = rb * n_wr + wr.
+template <int WAVES, int GROUP>
+__global__ void __launch_bounds__(64 * WAVES)
+k_label_tiles(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_row,
+              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Oc, uint64_t oc_word_stride,
+              uint32_t n_words, uint32_t n_wr, uint32_t wr_words, uint64_t n_traj, uint64_t max_entry,
+              uint64_t *__restrict__ P, uint64_t p_stride)
+{
+    extern __shared__ uint64_t lds[];
+    tile_body<WAVES, GROUP>(seg, sp_row, sp_val, Oc, oc_word_stride, n_words, blockIdx.x / n_wr, blockIdx.x % n_wr,
+                            wr_words, n_traj, max_entry, P, p_stride, lds);
+}
+
+// One workgroup per (pass, tile, lane group) of a batch.  The pass's cell
+// masks are [w][G64][64] (cell-indexed), its partials [G64][n_wr][rows].
+template <int WAVES, int GROUP>
+__global__ void __launch_bounds__(64 * WAVES)
+k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items)
+{
+    extern __shared__ uint64_t lds[];
+    const TileItem it = items[blockIdx.x];
+    const GroupDesc &g = groups[it.group];
+    const uint64_t p_stride = (uint64_t)g.n_rb * kRowBlock;
+    tile_body<WAVES, GROUP>(g.sp_seg, g.sp_row, g.sp_val, g.Ow + (uint64_t)it.gi * 64, (uint64_t)g.G64 * 64, g.n_words,
+                            it.rb, it.wr, g.wr_words, g.n_traj, g.max_entry,
+                            g.P + (uint64_t)it.gi * g.n_wr * p_stride, p_stride, lds);
+}
+
+// One wavefront per (pass, lane group, rows [row0, row1)): lane l holds the
+// descriptor of column (gi, l); 64 rows at a time, lane j ORs the partials
+// of row t0 + j, then every row's bits are broadcast and each lane writes its
+// column's byte into its job's L.
+__global__ void __launch_bounds__(64)
+k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restrict__ items)
+{
+    const uint32_t lane = threadIdx.x;
+    const CombineItem it = items[blockIdx.x];
+    const GroupDesc &g = groups[it.group];
+    const LaneDesc d = g.lanes[it.gi * 64 + lane];
+    const uint64_t p_stride = (uint64_t)g.n_rb * kRowBlock;
+    const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_wr * p_stride;
+    for (uint64_t t0 = it.row0; t0 < it.row1; t0 += 64) {
+        const uint64_t t = t0 + lane;
+        uint64_t bits = 0;
+        if (t < it.row1)
+            for (uint32_t r = 0; r < g.n_wr; ++r) bits |= Pg[(uint64_t)r * p_stride + t];
+        const uint32_t n = (uint32_t)min<uint64_t>(64, it.row1 - t0);
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)bits, j);
+            const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), j);
+            const uint64_t b = ((uint64_t)hi << 32) | lo;
+            if (d.L) d.L[(t0 + j) * d.n_props] = (uint8_t)((b >> lane) & 1ull);
+        }
+    }
+}
+
 __device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204081u) & 0x01010101u; }
 
 // One thread per row: OR of the row's partials (coalesced over rows), then
@@ -327,6 +382,21 @@ size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr size_t kTileLds = (kRowBlock + (size_t)kTileWaves * kWordGroup * 256) * sizeof(uint64_t);
 
 }  // namespace
+
+hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, uint32_t n_tiles, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_label_tiles_batch<kTileWaves, kWordGroup>), dim3(n_tiles), dim3(64 * kTileWaves), kTileLds, s,
+                       d_groups, d_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine_batch(const GroupDesc *d_groups, const CombineItem *d_items, uint32_t n_items, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine_batch, dim3(n_items), dim3(64), 0, s, d_groups, d_items);
+    return hipGetLastError();
+}
 
 lbl_status build_sparse(lbl_abs *a)
 {

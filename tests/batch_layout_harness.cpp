@@ -9,8 +9,10 @@
 #include <map>
 #include <random>
 #include <set>
+#include <tuple>
 
 #include "batch.h"
+#include "sparse.h"
 
 using namespace lbl;
 
@@ -67,7 +69,10 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
         CHECK(it.row1 - it.row0 <= (uint64_t)tile.rows_per_item);
         covered[it.group] += it.row1 - it.row0;
     }
-    for (size_t g = 0; g < p.groups.size(); ++g) CHECK(covered[g] == p.groups[g].n_traj);
+    if (!p.sparse)
+        for (size_t g = 0; g < p.groups.size(); ++g) CHECK(covered[g] == p.groups[g].n_traj);
+    else
+        CHECK(p.items.empty());
     // lanes: every (job, proposition) exactly once, with its own stride
     std::map<const uint8_t *, int> seen;
     for (const LaneDesc &d : p.lanes)
@@ -81,6 +86,49 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     uint64_t pairs = 0;
     for (const JobRef &j : jobs) pairs += j.a->n_traj * j.n_props;
     CHECK(p.pairs == pairs);
+    // sparse plans: partial regions inside and disjoint, every tile once,
+    // every row of every lane group combined once
+    bool sparse = true;
+    for (const JobRef &j : jobs) sparse = sparse && j.a->sp_seg != nullptr;
+    CHECK(p.sparse == sparse);
+    if (!p.sparse) return;
+    std::vector<std::pair<const uint8_t *, const uint8_t *>> p_ranges;
+    std::set<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>> tiles;
+    uint64_t want_tiles = 0;
+    for (size_t g = 0; g < p.groups.size(); ++g) {
+        const GroupDesc &d = gs[g];
+        CHECK(d.n_rb == (uint32_t)((d.n_traj + kRowBlock - 1) / kRowBlock));
+        CHECK(d.n_wr >= 1 && (uint64_t)d.n_wr * d.wr_words >= d.n_words && (d.n_wr - 1) * d.wr_words < d.n_words);
+        const size_t pb = (size_t)d.G64 * d.n_wr * d.n_rb * kRowBlock * sizeof(uint64_t);
+        CHECK(inside(d.P, pb));
+        p_ranges.push_back({reinterpret_cast<const uint8_t *>(d.P), reinterpret_cast<const uint8_t *>(d.P) + pb});
+        want_tiles += (uint64_t)d.n_rb * d.n_wr * d.G64;
+    }
+    for (size_t i = 0; i < p_ranges.size(); ++i) {
+        CHECK(p_ranges[i].second <= ow_ranges.front().first || p_ranges[i].first >= ow_ranges.back().second);
+        for (size_t j = i + 1; j < p_ranges.size(); ++j)
+            CHECK(p_ranges[i].second <= p_ranges[j].first || p_ranges[j].second <= p_ranges[i].first);
+    }
+    CHECK(inside(b.d_tiles, p.tiles.size() * sizeof(TileItem)));
+    CHECK(inside(b.d_combines, p.combines.size() * sizeof(CombineItem)));
+    for (const TileItem &t : p.tiles) {
+        CHECK(t.group < p.groups.size());
+        const GroupDesc &d = p.groups[t.group];
+        CHECK(t.rb < d.n_rb && t.wr < d.n_wr && t.gi < d.G64);
+        tiles.insert(std::make_tuple(t.group, t.rb, t.wr, t.gi));
+    }
+    CHECK(tiles.size() == p.tiles.size() && p.tiles.size() == want_tiles);
+    std::map<std::pair<uint32_t, uint32_t>, uint64_t> rows;
+    for (const CombineItem &c : p.combines) {
+        CHECK(c.group < p.groups.size() && c.gi < p.groups[c.group].G64);
+        CHECK(c.row0 < c.row1 && c.row1 <= p.groups[c.group].n_traj && c.row0 % 64 == 0);
+        rows[std::make_pair(c.group, c.gi)] += c.row1 - c.row0;
+    }
+    for (size_t g = 0; g < p.groups.size(); ++g)
+        for (uint32_t gi = 0; gi < p.groups[g].G64; ++gi) {
+            const uint64_t covered_rows = rows[std::make_pair((uint32_t)g, gi)];
+            CHECK(covered_rows == p.groups[g].n_traj);
+        }
 }
 
 int main()
@@ -117,6 +165,29 @@ int main()
             fake += 0x2000000000ull;
         }
     check_case(abss, jobs, BatchTile{4, 16, 32});
+    // the same batches with the sparse layout present on every abstraction
+    for (int i = 0; i < 6; ++i) {
+        abss[i].sp_seg = reinterpret_cast<uint64_t *>(0x300000000000ull + 0x10000000ull * i);
+        abss[i].sp_row = reinterpret_cast<uint16_t *>(0x310000000000ull + 0x10000000ull * i);
+        abss[i].sp_val = reinterpret_cast<uint64_t *>(0x320000000000ull + 0x10000000ull * i);
+        abss[i].sp_nnz = rows[i] * 50;
+        abss[i].sp_geom.n_rb = (uint32_t)((rows[i] + kRowBlock - 1) / kRowBlock);
+    }
+    check_case(abss, jobs, BatchTile{});
+    for (int trial = 0; trial < 10; ++trial) {
+        std::vector<JobRef> js;
+        const int n = 1 + (int)(rng() % 120);
+        for (int k = 0; k < n; ++k) {
+            lbl_abs *a = &abss[rng() % 6];
+            js.push_back(JobRef{a, fake, 1 + (uint32_t)(rng() % 64), fake + 0x1000000000ull});
+            fake += 0x2000000000ull;
+        }
+        check_case(abss, js, BatchTile{});
+    }
+    // a batch mixing an abstraction without the sparse layout is planned bitpacked
+    abss[2].sp_seg = nullptr;
+    check_case(abss, jobs, BatchTile{});
+    abss[2].sp_seg = reinterpret_cast<uint64_t *>(0x300000000000ull + 0x20000000ull);
     // invalid jobs are rejected without touching anything
     BatchPlan p;
     JobRef bad{&abss[0], nullptr, 8, fake};
