@@ -112,9 +112,9 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
 
     bits    : dense bitpacked T (8 B per 64-cell word of every row) + packed
               frame masks (W x 64 x 8 B) + L (1 B per pair)          -> HBM
-    sparse  : sparse layout (12 B per (row, word) entry + word pointers +
-              chunk table) + cell masks (W x 64 x 8 B) + label bits
-              (8 B per row)                                           -> HBM
+    sparse  : sparse layout (10 B per (row, word) entry + the one-frame
+              tiling's task and round tables) + cell masks (W x 64 x 8 B)
+              + label bits (8 B per row)                              -> HBM
     mfma    : 2 N_t N_c N_p int8 multiply-adds                         -> MFMA
     mfma_i8 : int8 T (1 B per cell of every row) + masks + L           -> HBM
     """
@@ -126,7 +126,7 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
                 "frac": ops / t / 1e12 / INT8_PEAK_TOPS, "traffic": None, "kernel": "label_mfma",
                 "kernel_ms": kernel_ms, "algorithmic_ops": ops}
     if kernel == "sparse":
-        alg, src, summary = info["sparse_bytes"] + W * 64 * 8 + n_traj * 8, "sparse.hip", "label_sparse_200k_512_64_traffic.json"
+        alg, src, summary = info["sparse_frame_bytes"] + W * 64 * 8 + n_traj * 8, "sparse.hip", "label_sparse_200k_512_64_traffic.json"
     elif kernel == "mfma_i8":
         alg, src, summary = n_traj * W * 64 + W * 64 * 8 + n_traj * n_props, "label_mfma.hip", None
     else:

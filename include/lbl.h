@@ -69,14 +69,15 @@ typedef struct {
 /* ---- flags for lbl_load_abstraction* ---------------------------------- */
 #define LBL_LOAD_KEEP_INT8 0x1u    /* also keep an int8 copy of T (N_t x N_c bytes) */
 #define LBL_LOAD_INPUT_DEVICE 0x2u /* the input arrays are device pointers */
-#define LBL_LOAD_NO_SPARSE 0x4u    /* do not build the sparse word-major layout */
+#define LBL_LOAD_NO_SPARSE 0x4u    /* do not build the sparse tiled layout */
 
 /* ---- flags for lbl_label_frame / lbl_label_batch ---------------------- */
 #define LBL_HOST_PTRS 0x1u      /* O and L are host pointers; the call is synchronous */
 #define LBL_KERNEL_AUTO 0x00u   /* kernel and tile chosen by the autotuner cache */
 #define LBL_KERNEL_BITS 0x10u   /* bitpacked AND/OR wavefront kernel (dense bitpacked T) */
-#define LBL_KERNEL_SPARSE 0x80u /* sparse word-major T, nibble tables per word
-                                   (needs the sparse layout, built by default) */
+#define LBL_KERNEL_SPARSE 0x80u /* sparse tiled T (non-zero words only), nibble
+                                   tables per word (needs the sparse layout,
+                                   built by default) */
 #define LBL_KERNEL_MFMA 0x20u   /* int8 MFMA kernel, T expanded from its bitpacked copy */
 #define LBL_KERNEL_MFMA_I8 0x40u /* int8 MFMA kernel reading the int8 copy of T
                                    (needs LBL_LOAD_KEEP_INT8) */
@@ -124,7 +125,12 @@ typedef struct {
     uint64_t nonzero_words;  /* words of the bitpacked T holding at least one set cell */
     uint64_t set_cells;      /* distinct (trajectory, cell) pairs set in T */
     uint64_t sparse_entries; /* (row, word) entries of the sparse layout (0 if not built) */
-    uint64_t sparse_bytes;   /* device bytes of the sparse layout */
+    uint64_t sparse_bytes;   /* device bytes of the sparse layout (entries and tilings) */
+    uint64_t sparse_frame_bytes; /* bytes one frame reads from it: every entry
+                                    (16-bit row, 64-bit word) and the one-frame
+                                    tiling's task and round tables */
+    uint32_t sparse_tiles;   /* workgroups of a one-frame launch */
+    uint32_t sparse_row_block; /* rows per row block of the sparse layout */
 } lbl_abs_info;
 
 lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);

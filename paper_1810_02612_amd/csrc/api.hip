@@ -136,9 +136,8 @@ static void abs_release(lbl_abs *a)
     (void)hipFree(a->T_i8);
     (void)hipFree(a->d_tile_word);
     (void)hipFree(a->d_word_cell);
-    (void)hipFree(a->sp_seg);
-    (void)hipFree(a->sp_row);
-    (void)hipFree(a->sp_val);
+    free_sparse(a->sp);
+    a->sp = nullptr;
     (void)hipSetDevice(cur);
 }
 
@@ -348,10 +347,22 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
     out->int8_bytes = a->T_i8 ? a->n_traj * a->n_words * 64ull : 0;
     out->nonzero_words = a->nonzero_words;
     out->set_cells = a->set_cells;
-    out->sparse_entries = a->sp_seg ? a->sp_nnz : 0;
-    out->sparse_bytes = a->sp_seg ? a->sp_nnz * (sizeof(uint16_t) + sizeof(uint64_t)) +
-                                        (a->sp_geom.n_rb * (uint64_t)a->n_words + 1) * sizeof(uint64_t)
-                                  : 0;
+    out->sparse_entries = 0;
+    out->sparse_bytes = 0;
+    out->sparse_frame_bytes = 0;
+    out->sparse_tiles = 0;
+    out->sparse_row_block = 0;
+    if (a->sp) {
+        const SparseLayout &sp = *a->sp;
+        const SpTiling &t = sp.tilings[0];
+        const uint64_t entry_bytes = sp.nnz * (sizeof(uint16_t) + sizeof(uint64_t));
+        out->sparse_entries = sp.nnz;
+        out->sparse_bytes = entry_bytes + sp.round_bytes;
+        out->sparse_frame_bytes = entry_bytes + (uint64_t)t.n_tiles * kTileWaves * sizeof(SpTask) +
+                                  t.n_rounds * sizeof(SpRound);
+        out->sparse_tiles = t.n_tiles;
+        out->sparse_row_block = kRowBlock;
+    }
     return LBL_OK;
 }
 
@@ -369,7 +380,7 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
                 "unknown kernel flag");
     LBL_REQUIRE(kflag != LBL_KERNEL_MFMA_I8 || a->T_i8 != nullptr,
                 "LBL_KERNEL_MFMA_I8 needs an abstraction loaded with LBL_LOAD_KEEP_INT8");
-    LBL_REQUIRE(kflag != LBL_KERNEL_SPARSE || a->sp_seg != nullptr,
+    LBL_REQUIRE(kflag != LBL_KERNEL_SPARSE || a->sp != nullptr,
                 "LBL_KERNEL_SPARSE needs the sparse layout (loaded without LBL_LOAD_NO_SPARSE, fewer than 2^32 rows)");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     int cur = 0;

@@ -6,6 +6,9 @@
 
 namespace lbl {
 
+struct SpTask;
+struct SpRound;
+
 // Per output lane (one proposition column of one frame).
 struct LaneDesc {
     const uint8_t *O;  // &O_job[p] (cell c at O[c * n_props]), null for an unused lane
@@ -27,20 +30,22 @@ struct GroupDesc {
     uint32_t row_stride;
     uint32_t n_words;
     uint32_t G64;
-    uint32_t n_rb;            // sparse: row blocks
-    // sparse tiled layout of T and this pass's partial labels
-    const uint64_t *sp_seg;
+    // sparse plans: the tiling of T's sparse layout this pass runs on, and
+    // the pass's partial labels
+    const SpTask *sp_tasks;
+    const SpRound *sp_rounds;
+    const uint32_t *sp_rb_tile;  // [n_rb + 1] first tile of each row block
     const uint16_t *sp_row;
     const uint64_t *sp_val;
     uint64_t max_entry;
-    uint64_t *P;              // [G64][n_wr][n_rb * kRowBlock]
-    uint32_t n_wr;
-    uint32_t wr_words;
+    uint64_t *P;                 // [G64][n_tiles][kRowBlock]
+    uint32_t n_tiles;
+    uint32_t n_rb;
 };
 
 // Sparse plans: one workgroup per (group, tile, lane group).
 struct TileItem {
-    uint32_t group, rb, wr, gi;
+    uint32_t group, tile, gi, pad;
 };
 
 // Sparse plans: one wavefront per (group, lane group, 64-row chunk range).
@@ -87,6 +92,8 @@ struct BatchPlan {
     size_t p_bytes = 0;
     std::vector<TileItem> tiles;
     std::vector<CombineItem> combines;
+    std::vector<const lbl_abs *> group_abs;  // abstraction of each group
+    int tiling = 0;                 // sparse: index of the tilings every pass uses
 
     bool finalized = false;         // tile set and items made
 

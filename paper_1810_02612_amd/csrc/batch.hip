@@ -175,19 +175,6 @@ size_t batch_table_bytes(const BatchPlan &p)
 
 size_t BatchPlan::device_bytes() const { return batch_table_bytes(*this) + ow_bytes + p_bytes; }
 
-// Word ranges per tile for a sparse pass with G lane groups: about
-// kTilesPerPass tiles per pass, at least kTileWaves words per tile, and at
-// most 8 ranges so that the partials (G x ranges x row blocks of kRowBlock
-// rows) stay a small multiple of the labels themselves.
-static uint32_t batch_word_ranges(const lbl_abs *a, uint32_t G)
-{
-    const uint32_t kTilesPerPass = 512, kMaxRanges = 8;
-    const uint64_t per = (uint64_t)a->sp_geom.n_rb * G;
-    uint32_t n_wr = (uint32_t)std::max<uint64_t>(1, (kTilesPerPass + per - 1) / per);
-    n_wr = std::min(n_wr, kMaxRanges);
-    return std::min<uint32_t>(n_wr, std::max<uint32_t>(1, a->n_words / (kTileWaves * kWordGroup)));
-}
-
 lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *out)
 {
     LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
@@ -202,7 +189,7 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
         LBL_REQUIRE(device < 0 || r.a->device == device, "job " + std::to_string(j) + ": abstraction lives on another device");
         if (!by_abs.count(r.a)) order.push_back(r.a);
         by_abs[r.a].push_back(j);
-        all_sparse = all_sparse && r.a->sp_seg != nullptr;
+        all_sparse = all_sparse && r.a->sp != nullptr;
     }
     BatchPlan &p = *out;
     p = BatchPlan{};
@@ -224,16 +211,10 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             g.n_words = a->n_words;
             g.G64 = (P + 63) / 64;
             if (p.sparse) {
-                g.n_rb = a->sp_geom.n_rb;
-                g.sp_seg = a->sp_seg;
-                g.sp_row = a->sp_row;
-                g.sp_val = a->sp_val;
-                g.max_entry = std::max<uint64_t>(a->sp_nnz, 1) - 1;
-                g.n_wr = batch_word_ranges(a, g.G64);
-                g.wr_words = (a->n_words + g.n_wr - 1) / g.n_wr;
-                g.n_wr = (a->n_words + g.wr_words - 1) / g.wr_words;
-                p.p_off.push_back(p.p_bytes);
-                p.p_bytes += up256((size_t)g.G64 * g.n_wr * g.n_rb * kRowBlock * sizeof(uint64_t));
+                g.n_rb = a->sp->n_rb;
+                g.sp_row = a->sp->row;
+                g.sp_val = a->sp->val;
+                g.max_entry = std::max<uint64_t>(a->sp->nnz, 1) - 1;
             }
             p.lane_off.push_back(p.lanes.size());
             p.lanes.resize(p.lanes.size() + (size_t)g.G64 * 64, LaneDesc{nullptr, nullptr, 0, 0});
@@ -248,13 +229,39 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             p.pack_units += (uint64_t)a->n_words * g.G64;
             p.max_g64 = std::max(p.max_g64, g.G64);
             p.groups.push_back(g);
+            p.group_abs.push_back(a);
             keys.push_back("W" + std::to_string(a->n_words) + "G" + std::to_string(g.G64));
             k = k1;
         }
     }
     std::sort(keys.begin(), keys.end());
     for (auto &s : keys) p.shape_key += s + ";";
-    if (p.sparse) p.shape_key = "sparse;" + p.shape_key;
+    if (p.sparse) {
+        // the coarsest tiling (fewest partials) that still gives every CU
+        // about two tile workgroups
+        const uint64_t want = 2ull * (uint64_t)device_cu_count();
+        p.tiling = kBatchTilings;
+        for (int t = 1; t <= kBatchTilings; ++t) {
+            uint64_t n = 0;
+            for (size_t g = 0; g < p.groups.size(); ++g)
+                n += (uint64_t)p.groups[g].G64 * p.group_abs[g]->sp->tilings[t].n_tiles;
+            if (n >= want) {
+                p.tiling = t;
+                break;
+            }
+        }
+        for (size_t g = 0; g < p.groups.size(); ++g) {
+            GroupDesc &d = p.groups[g];
+            const SpTiling &tl = p.group_abs[g]->sp->tilings[p.tiling];
+            d.sp_tasks = tl.tasks;
+            d.sp_rounds = tl.rounds;
+            d.sp_rb_tile = tl.rb_tile;
+            d.n_tiles = tl.n_tiles;
+            p.p_off.push_back(p.p_bytes);
+            p.p_bytes += up256((size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t));
+        }
+        p.shape_key = "sparse" + std::to_string(p.tiling) + ";" + p.shape_key;
+    }
     return LBL_OK;
 }
 
@@ -270,14 +277,13 @@ void plan_finalize(BatchPlan &p, const BatchTile &tile)
         // tiles of the passes with the most entries per tile first
         auto cost = [&](uint32_t g) {
             const GroupDesc &d = p.groups[g];
-            return (double)(d.max_entry + 1) / ((double)d.n_rb * d.n_wr);
+            return (double)(d.max_entry + 1) / (double)d.n_tiles;
         };
         std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
         for (uint32_t g : idx) {
             const GroupDesc &d = p.groups[g];
-            for (uint32_t rb = 0; rb < d.n_rb; ++rb)
-                for (uint32_t wr = 0; wr < d.n_wr; ++wr)
-                    for (uint32_t gi = 0; gi < d.G64; ++gi) p.tiles.push_back(TileItem{g, rb, wr, gi});
+            for (uint32_t t = 0; t < d.n_tiles; ++t)
+                for (uint32_t gi = 0; gi < d.G64; ++gi) p.tiles.push_back(TileItem{g, t, gi, 0});
         }
         const uint64_t R = 512;  // rows per combine item (a multiple of 64)
         for (uint32_t g = 0; g < p.groups.size(); ++g)

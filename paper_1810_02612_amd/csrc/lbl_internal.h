@@ -48,13 +48,9 @@ struct CellOrder {
 
 uint32_t morton2(uint32_t x, uint32_t y);  // x bits at odd positions
 
-// Geometry of the sparse tiled layout: tiles are (row block, word range).
-struct SparseGeom {
-    uint32_t n_rb = 0;      // row blocks
-    uint32_t n_wr = 0;      // word ranges
-    uint32_t wr_words = 0;  // words per word range
-    uint64_t n_tiles() const { return (uint64_t)n_rb * n_wr; }
-};
+// Sparse tiled layout of T (defined with its kernels).
+struct SparseLayout;
+void free_sparse(SparseLayout *sp);
 
 }  // namespace lbl
 
@@ -75,11 +71,7 @@ struct lbl_abs {
     uint64_t set_cells = 0;
     lbl::CellOrder order;
     // sparse tiled layout (null when not built)
-    uint64_t *sp_seg = nullptr;  // [n_rb * n_words + 1] entry offsets of segments (rb, w)
-    uint16_t *sp_row = nullptr;  // [sp_nnz] row within the row block
-    uint64_t *sp_val = nullptr;  // [sp_nnz] word value
-    uint64_t sp_nnz = 0;
-    lbl::SparseGeom sp_geom;
+    lbl::SparseLayout *sp = nullptr;
 };
 
 namespace lbl {

@@ -2,26 +2,92 @@
 #pragma once
 
 #include <memory>
+#include <vector>
 
 #include "lbl_internal.h"
 
 namespace lbl {
 
-// Rows per row block of a tile (local rows fit in 16 bits).
-constexpr uint32_t kRowBlock = 4096;
-// Consecutive words whose nibble tables a wavefront holds at once.
-constexpr uint32_t kWordGroup = 1;
-// Wavefronts per tile workgroup.
-constexpr uint32_t kTileWaves = 4;
+// Rows per row block (local rows fit in 16 bits; a block's accumulators fill
+// 64 KB of LDS).
+constexpr uint32_t kRowBlock = 8192;
+// Wavefronts per tile workgroup (one workgroup per CU: 16 wavefronts).
+constexpr uint32_t kTileWaves = 16;
+// Nibble tables a wavefront holds at once (a round touches at most two
+// segments).
+constexpr uint32_t kRing = 2;
+// LDS of a tile workgroup: accumulators + every wavefront's tables.
+constexpr size_t kTileLds = ((size_t)kRowBlock + (size_t)kTileWaves * kRing * 256) * sizeof(uint64_t);
 
-// Build the tiled layout of a from its bitpacked T.
+// One wavefront's share of a tile: consecutive entries lo .. of one row
+// block, processed as rounds [round0, round0 + n_rounds).
+struct SpTask {
+    uint64_t lo;
+    uint32_t n_rounds;
+    uint32_t round0;
+};
+
+// One round: up to 64 consecutive entries, lane l taking entry
+// task.lo + e_off + l, each lane in one of two segments (words).
+struct SpRound {
+    uint32_t e_off;  // multiple of 64
+    uint32_t word0;  // word of the first segment
+    uint32_t word1;  // word of the second segment (word0 when unused)
+    uint32_t meta;   // lane_lo | lane_hi << 8 | cut << 16 | build0 << 24 | build1 << 25 | slot0 << 26
+};
+constexpr uint32_t kMetaBuild0 = 1u << 24, kMetaBuild1 = 1u << 25, kMetaSlot0 = 1u << 26;
+
+// A split of the layout into tiles: kTileWaves tasks per tile, every tile in
+// one row block; rb_tile[rb] .. rb_tile[rb + 1] are the tiles of block rb.
+struct SpTiling {
+    uint32_t n_tiles = 0;
+    uint64_t n_rounds = 0;
+    SpTask *tasks = nullptr;     // device [n_tiles * kTileWaves]
+    SpRound *rounds = nullptr;   // device [n_rounds]
+    uint32_t *rb_tile = nullptr; // device [n_rb + 1]
+    std::vector<uint32_t> rb_tile_host;
+};
+
+// Device-resident sparse layout of one abstraction.
+struct SparseLayout {
+    uint32_t n_rb = 0;
+    uint64_t nnz = 0;            // entries (non-zero words of T)
+    uint64_t n_segments = 0;     // non-empty (row block, word) segments
+    uint16_t *row = nullptr;     // device [nnz] row within the row block
+    uint64_t *val = nullptr;     // device [nnz] word value
+    // tilings[0]: one frame (about one tile per CU, tiles of equal cost);
+    // tilings[1 + i]: 2^i tiles per row block (batches)
+    std::vector<SpTiling> tilings;
+    size_t round_bytes = 0;      // device bytes of all tilings' tables
+    ~SparseLayout();
+};
+
+constexpr int kBatchTilings = 4;  // 1, 2, 4, 8 tiles per row block
+
+// Build the tiled layout of a from its bitpacked T (sets a->sp).
 lbl_status build_sparse(lbl_abs *a);
 
-// Workspace bytes for one frame of n_lane_groups 64-column groups
-// (cell masks + per-tile partial labels).
-size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1);
+// Workspace bytes for one frame of n_lane_groups 64-column groups on tiling
+// t (cell masks + per-tile partial labels).
+size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t = 0);
 
 // Pack O, label through the tiled layout, write L (device pointers).
 lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s);
+
+// Host-side: the tasks and rounds of one tiling of a row-block-ordered
+// segment list (exposed for host tests).  seg_start[s] .. seg_start[s + 1]
+// are the entries of segment s, seg_word[s] its word, rb_seg[rb] ..
+// rb_seg[rb + 1] the segments of row block rb.  tiles_rb[rb] >= 1 tiles per
+// row block.
+struct TilingHost {
+    std::vector<SpTask> tasks;
+    std::vector<SpRound> rounds;
+    std::vector<uint32_t> rb_tile;
+};
+void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
+                 const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out);
+// Tiles per row block for about `target` tiles of equal cost in total.
+std::vector<uint32_t> tiles_per_block(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
+                                      uint32_t target);
 
 }  // namespace lbl

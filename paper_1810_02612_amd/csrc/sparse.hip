@@ -3,30 +3,38 @@
 // Layout.  Every non-zero 64-cell word of T becomes one entry (local row,
 // word value).  Entries are grouped into segments (row block rb, word w):
 // the rows of block rb (kRowBlock rows) whose swept set meets word w,
-// ascending.  Segments are stored in (rb, w) order, so the entries of a tile
-// (row block rb, a range of consecutive words) are contiguous, and
-// seg[rb * W + w] .. seg[rb * W + w + 1] delimits one segment.  This is the
-// compressed-sparse idea of Sec. 4.3 (store only the true entries of M) at
-// word granularity, ordered so that the frame data a word needs is prepared
-// once per tile and shared by every trajectory of the tile that crosses it.
+// ascending; only non-empty segments exist, stored in (rb, w) order, so the
+// entries of one row block are contiguous.  This is the compressed-sparse
+// idea of Sec. 4.3 (store only the true entries of M) at word granularity,
+// ordered so that the frame data a word needs is prepared once per row
+// block and shared by every trajectory of the block that crosses it.
+//
+// Tilings (built on the host at load time).  A row block's entries are cut
+// into wavefront tasks of equal cost (entries plus a charge per segment
+// started), kTileWaves tasks to a tile (one workgroup).  A task is walked in
+// rounds of 64 consecutive entries, one per lane; a round whose entries
+// span more than two segments is split so that each round touches at most
+// two.  Each round carries which lanes are active, which lanes fall in its
+// second segment, and which of its segments' tables must be built first.
 //
 // Per frame:
 //   k_pack_cells   O -> Oc[w][b]: 64-bit mask of the propositions that cell
 //                  b of word w meets (one lane per cell).
-//   k_label_tiles  one workgroup per tile.  Each wavefront takes groups of
-//                  kWordGroup consecutive words of the tile, builds in LDS
-//                  their 16 x 16 nibble tables (entry [n][v] = OR of Oc over
-//                  the cells 4n + b with bit b of v set), and every lane
-//                  takes one entry (row t, word value x) and ORs the 16
-//                  table entries selected by the nibbles of x: the labels of
-//                  that (row, word) pair for up to 64 propositions.  They are
-//                  OR-ed into the tile's per-row accumulators with LDS atomics
-//                  and written once per row as the tile's partial label.
-//   k_combine      OR of a row's partials over the word ranges -> the
-//                  caller's L bytes (0/1).
+//   k_label_tiles  one workgroup per tile.  A wavefront keeps the 16 x 16
+//                  nibble tables of two segments in LDS (entry [n][v] = OR
+//                  of Oc over the cells 4n + b with bit b of v set), building
+//                  a segment's table when a round first reaches it; every
+//                  active lane ORs the 16 table entries selected by the
+//                  nibbles of its word value (the labels of that (row, word)
+//                  pair for up to 64 propositions) into the tile's per-row
+//                  accumulators with an LDS atomic.  The accumulators are
+//                  written once per tile as its partial labels.
+//   k_combine      OR of a row's partials over the tiles of its row block ->
+//                  the caller's L bytes (0/1).
 // OR is idempotent and commutative, so neither the order of the LDS atomics
 // nor the split into tiles changes the result.  No global atomics are used.
 #include <algorithm>
+#include <cmath>
 
 #include "batch.h"
 #include "profile.h"
@@ -166,144 +174,163 @@ k_pack_cells(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__
     Oc[idx] = m;
 }
 
-// One workgroup per tile (row block rb, word range wr).  Oc_word(w) =
-// Oc + w * oc_word_stride holds the 64 cell masks of word w.  Writes the
-// tile's partial labels to P[wr * p_stride + row] for its rows.
-template <int WAVES, int GROUP>
-__device__ __forceinline__ void tile_body(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_row,
-                                          const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Oc,
-                                          uint64_t oc_word_stride, uint32_t n_words, uint32_t rb, uint32_t wr,
-                                          uint32_t wr_words, uint64_t n_traj, uint64_t max_entry,
-                                          uint64_t *__restrict__ P, uint64_t p_stride, uint64_t *lds)
+
+// Value of lane C of each group of four lanes (DPP quad permutation).
+template <int C>
+__device__ __forceinline__ uint64_t quad_bcast(uint64_t v)
 {
-    const uint32_t lane = threadIdx.x & 63;
-    // uniform across the wavefront: segment bounds become scalar loads and
-    // the per-group branches scalar branches
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t *acc = lds;                                      // kRowBlock accumulators
-    uint64_t *tab = lds + kRowBlock + wave * (GROUP * 256);   // this wavefront's tables
-    for (uint32_t i = threadIdx.x; i < kRowBlock; i += blockDim.x) acc[i] = 0ull;
-    __syncthreads();
-    const uint32_t w_lo = wr * wr_words, w_hi = min(w_lo + wr_words, n_words);
-    const uint64_t *segb = seg + (uint64_t)rb * n_words;
-    const uint32_t nib = lane >> 2, v0 = (lane & 3u) * 4;
-
-    // Everything a word group needs, loaded one group ahead so that the
-    // latency of the next group's loads overlaps this group's work.
-    struct Group {
-        uint64_t lo, hi;           // entry range of the group (uniform)
-        uint64_t bound[GROUP];     // end of each word's segment (uniform)
-        uint64_t o[GROUP][4];      // this lane's 4 cell masks of each word
-        uint64_t x;                // first entry of this lane (valid if lo + lane < hi)
-        uint32_t r;
-        uint32_t nw;
-    };
-    // Every load is unconditional at a clamped, in-bounds address (branches
-    // around loads would make the compiler wait for all of them); validity
-    // is applied when the group is processed.
-    const uint64_t last_entry = max_entry;  // last valid index of sp_val / sp_row
-    auto fetch = [&](Group &d, uint32_t w0) {
-        const uint32_t ws = min(w0, w_hi);  // w0 >= w_hi: an empty group at w_hi
-        d.nw = min((uint32_t)GROUP, w_hi - ws);
-        d.lo = segb[ws];
-        d.hi = segb[ws + d.nw];
-#pragma unroll
-        for (int j = 0; j < GROUP; ++j) {
-            const uint32_t wj = min(ws + (uint32_t)j, w_hi - 1);
-            d.bound[j] = segb[min(ws + (uint32_t)j + 1, ws + d.nw)];
-            const uint64_t *cell = Oc + (uint64_t)wj * oc_word_stride + 4 * nib;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) d.o[j][c] = cell[c];
-        }
-        const uint64_t k = min(d.lo + lane, last_entry);
-        d.x = sp_val[k];
-        d.r = sp_row[k];
-    };
-
-    // Tables and lookups of one group whose loads have arrived.
-    auto process = [&](const Group &g) {
-        if (g.lo == g.hi) return;  // uniform
-        // nibble tables: lane l fills entries [nib][v0 + q] of each word's table
-#pragma unroll
-        for (int j = 0; j < GROUP; ++j) {
-            if ((uint32_t)j >= g.nw) break;
-#pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-                const uint32_t v = v0 + q;
-                uint64_t e = (v & 1u) ? g.o[j][0] : 0ull;
-                e |= (v & 2u) ? g.o[j][1] : 0ull;
-                e |= (v & 4u) ? g.o[j][2] : 0ull;
-                e |= (v & 8u) ? g.o[j][3] : 0ull;
-                tab[j * 256 + nib * 16 + v] = e;
-            }
-        }
-        // LDS instructions of a wavefront complete in issue order, so the
-        // lookups below see the whole table; the barrier only stops the
-        // compiler from moving LDS accesses across this point.
-        __builtin_amdgcn_wave_barrier();
-        auto lookup = [&](uint64_t k, uint64_t x, uint32_t r) {
-            uint32_t j = 0;
-#pragma unroll
-            for (int q = 0; q + 1 < GROUP; ++q) j += k >= g.bound[q] ? 1u : 0u;
-            const uint64_t *t = tab + j * 256;
-            const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-            uint64_t a = 0;
-#pragma unroll
-            for (int n = 0; n < 8; ++n) a |= t[n * 16 + ((lo >> (4 * n)) & 0xFu)];
-#pragma unroll
-            for (int n = 0; n < 8; ++n) a |= t[(n + 8) * 16 + ((hi >> (4 * n)) & 0xFu)];
-            if (a) __hip_atomic_fetch_or(acc + r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        };
-        // the first 64 entries were fetched with the group
-        if (g.lo + lane < g.hi) lookup(g.lo + lane, g.x, g.r);
-        // groups with more entries load the rest here
-        for (uint64_t k = g.lo + 64 + lane; k < g.hi; k += 64) lookup(k, sp_val[k], sp_row[k]);
-        __builtin_amdgcn_wave_barrier();  // the next group's tables overwrite these
-    };
-
-    // ping-pong between two groups so that one group's loads are in flight
-    // while the other is processed
-    const uint32_t step = WAVES * GROUP;
-    Group A, B;
-    fetch(A, w_lo + wave * GROUP);
-    for (uint32_t w0 = w_lo + wave * GROUP; w0 < w_hi; w0 += 2 * step) {
-        fetch(B, w0 + step);
-        process(A);
-        fetch(A, w0 + 2 * step);
-        process(B);
-    }
-    __syncthreads();
-    const uint64_t row0 = (uint64_t)rb * kRowBlock;
-    uint64_t *Pw = P + (uint64_t)wr * p_stride + row0;
-    for (uint32_t i = threadIdx.x; i < kRowBlock && row0 + i < n_traj; i += blockDim.x) Pw[i] = acc[i];
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, C * 0x55, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), C * 0x55, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// One workgroup per tile of a single frame: tile = rb * n_wr + wr.
-template <int WAVES, int GROUP>
+// Nibble tables of one word into t[16][16]; lane l holds the mask of cell l
+// of the word.  The four lanes of nibble n (cells 4n .. 4n + 3) share their
+// masks; lane 4n + j writes entries [n][j + 4m], m = 0..3.  Every lane of
+// the wavefront must be active.
+__device__ __forceinline__ void build_tables(uint64_t cell, uint64_t *t, uint32_t lane)
+{
+    const uint64_t o0 = quad_bcast<0>(cell), o1 = quad_bcast<1>(cell);
+    const uint64_t o2 = quad_bcast<2>(cell), o3 = quad_bcast<3>(cell);
+    const uint32_t j = lane & 3u;
+    const uint64_t lo = ((j & 1u) ? o0 : 0ull) | ((j & 2u) ? o1 : 0ull);
+    uint64_t *e = t + (lane >> 2) * 16 + j;
+    e[0] = lo;
+    e[4] = lo | o2;
+    e[8] = lo | o3;
+    e[12] = lo | o2 | o3;
+}
+
+// One tile: its wavefronts walk their tasks, OR-ing labels into the row
+// block's accumulators, then the accumulators become the tile's partials
+// Pt[0 .. kRowBlock).  Oc + w * oc_stride + b is the mask of cell b of word w.
+template <int WAVES>
+__device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds,
+                                          const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
+                                          uint64_t max_entry, const uint64_t *__restrict__ Oc, uint64_t oc_stride,
+                                          uint64_t tile, uint64_t *__restrict__ Pt, uint64_t *lds)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    // uniform across the wavefront: task fields and round records become
+    // scalars and the per-round branches scalar branches
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t *acc = lds;                                  // kRowBlock accumulators
+    uint64_t *tab = lds + kRowBlock + wave * (kRing * 256);  // this wavefront's two tables
+    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
+        reinterpret_cast<ulonglong2 *>(acc)[i] = make_ulonglong2(0ull, 0ull);
+    __syncthreads();
+    const SpTask tk = tasks[tile * WAVES + wave];
+    const uint32_t n = tk.n_rounds;
+    if (n > 0) {
+        const SpRound *rr = rounds + tk.round0;
+
+        struct Stage {
+            uint32_t e_off, meta;
+            uint64_t x;       // this lane's word value
+            uint32_t r;       // its local row
+            uint64_t c0, c1;  // this lane's cell of each segment's word
+        };
+        // Round records are read with scalar loads one round ahead of use.
+        // Every vector load is unconditional at a clamped, in-bounds address
+        // (branches around loads would make the compiler wait for all of
+        // them); validity is applied when the round is processed.
+        SpRound rec_next = rr[0];
+        auto fetch = [&](Stage &st, uint32_t i) {
+            const SpRound rec = rec_next;
+            rec_next = rr[min(i + 1, n - 1)];
+            st.e_off = rec.e_off;
+            st.meta = rec.meta;
+            const uint64_t e = min(tk.lo + rec.e_off + lane, max_entry);
+            st.x = sp_val[e];
+            st.r = sp_row[e];
+            st.c0 = Oc[(uint64_t)rec.word0 * oc_stride + lane];
+            st.c1 = Oc[(uint64_t)rec.word1 * oc_stride + lane];
+        };
+
+        auto process = [&](const Stage &st) {
+            const uint32_t meta = st.meta;
+            const uint32_t s0 = (meta & kMetaSlot0) ? 1u : 0u;
+            if (meta & kMetaBuild0) build_tables(st.c0, tab + s0 * 256, lane);
+            if (meta & kMetaBuild1) build_tables(st.c1, tab + (s0 ^ 1u) * 256, lane);
+            // LDS instructions of a wavefront complete in issue order, so the
+            // lookups below see the whole table; the barrier only stops the
+            // compiler from moving LDS accesses across this point.
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t lane_lo = meta & 0xFFu, lane_hi = (meta >> 8) & 0xFFu, cut = (meta >> 16) & 0xFFu;
+            if (lane >= lane_lo && lane < lane_hi) {
+                const uint64_t *t = tab + (s0 ^ (lane >= cut ? 1u : 0u)) * 256;
+                const uint32_t lo = (uint32_t)st.x, hi = (uint32_t)(st.x >> 32);
+                uint64_t a = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a |= t[q * 16 + ((lo >> (4 * q)) & 0xFu)];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a |= t[(q + 8) * 16 + ((hi >> (4 * q)) & 0xFu)];
+                if (a) __hip_atomic_fetch_or(acc + st.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            __builtin_amdgcn_wave_barrier();  // later builds overwrite these tables
+            // the cell masks count as used here even when no table was built,
+            // so that their registers are not reused while their loads are in
+            // flight (which would make the next fetch wait for every load)
+            asm volatile("" ::"v"(st.c0), "v"(st.c1));
+        };
+
+        // ping-pong between two rounds so that one round's loads are in
+        // flight while the other is processed.  With n odd the last round is
+        // processed twice (fetch clamps to it), which changes nothing: its
+        // tables are rebuilt with the same contents and OR is idempotent.
+        Stage A, B;
+        fetch(A, 0);
+        for (uint32_t i = 0; i < n; i += 2) {
+            fetch(B, i + 1);
+            process(A);
+            fetch(A, i + 2);
+            process(B);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
+        reinterpret_cast<ulonglong2 *>(Pt)[i] = reinterpret_cast<const ulonglong2 *>(acc)[i];
+}
+
+// One workgroup per tile of a single frame.  Partials P[tile][kRowBlock].
+template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
-k_label_tiles(const uint64_t *__restrict__ seg, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Oc, uint64_t oc_word_stride,
-              uint32_t n_words, uint32_t n_wr, uint32_t wr_words, uint64_t n_traj, uint64_t max_entry,
-              uint64_t *__restrict__ P, uint64_t p_stride)
+k_label_tiles(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
+              const uint64_t *__restrict__ sp_val, uint64_t max_entry, const uint64_t *__restrict__ Oc,
+              uint64_t *__restrict__ P)
 {
     extern __shared__ uint64_t lds[];
-    tile_body<WAVES, GROUP>(seg, sp_row, sp_val, Oc, oc_word_stride, n_words, blockIdx.x / n_wr, blockIdx.x % n_wr,
-                            wr_words, n_traj, max_entry, P, p_stride, lds);
+    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Oc, 64, blockIdx.x, P + (uint64_t)blockIdx.x * kRowBlock,
+                     lds);
 }
 
 // One workgroup per (pass, tile, lane group) of a batch.  The pass's cell
-// masks are [w][G64][64] (cell-indexed), its partials [G64][n_wr][rows].
-template <int WAVES, int GROUP>
+// masks are [w][G64][64] (cell-indexed), its partials [G64][n_tiles][kRowBlock].
+template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items)
 {
     extern __shared__ uint64_t lds[];
     const TileItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    const uint64_t p_stride = (uint64_t)g.n_rb * kRowBlock;
-    tile_body<WAVES, GROUP>(g.sp_seg, g.sp_row, g.sp_val, g.Ow + (uint64_t)it.gi * 64, (uint64_t)g.G64 * 64, g.n_words,
-                            it.rb, it.wr, g.wr_words, g.n_traj, g.max_entry,
-                            g.P + (uint64_t)it.gi * g.n_wr * p_stride, p_stride, lds);
+    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.max_entry, g.Ow + (uint64_t)it.gi * 64,
+                     (uint64_t)g.G64 * 64, it.tile,
+                     g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
+}
+
+// OR of row t's partials over the tiles of its row block.
+__device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile,
+                                                 uint64_t t)
+{
+    const uint64_t rb = t / kRowBlock, loc = t % kRowBlock;
+    const uint32_t k0 = rb_tile[rb], k1 = rb_tile[rb + 1];
+    uint64_t bits = 0;
+    uint32_t k = k0;
+    for (; k + 4 <= k1; k += 4)
+        bits |= P[(uint64_t)k * kRowBlock + loc] | P[(uint64_t)(k + 1) * kRowBlock + loc] |
+                P[(uint64_t)(k + 2) * kRowBlock + loc] | P[(uint64_t)(k + 3) * kRowBlock + loc];
+    for (; k < k1; ++k) bits |= P[(uint64_t)k * kRowBlock + loc];
+    return bits;
 }
 
 // One wavefront per (pass, lane group, rows [row0, row1)): lane l holds the
@@ -317,13 +344,10 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
     const CombineItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
     const LaneDesc d = g.lanes[it.gi * 64 + lane];
-    const uint64_t p_stride = (uint64_t)g.n_rb * kRowBlock;
-    const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_wr * p_stride;
+    const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_tiles * kRowBlock;
     for (uint64_t t0 = it.row0; t0 < it.row1; t0 += 64) {
         const uint64_t t = t0 + lane;
-        uint64_t bits = 0;
-        if (t < it.row1)
-            for (uint32_t r = 0; r < g.n_wr; ++r) bits |= Pg[(uint64_t)r * p_stride + t];
+        const uint64_t bits = t < it.row1 ? row_partials(Pg, g.sp_rb_tile, t) : 0ull;
         const uint32_t n = (uint32_t)min<uint64_t>(64, it.row1 - t0);
         for (uint32_t j = 0; j < n; ++j) {
             const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)bits, j);
@@ -340,19 +364,14 @@ __device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204
 // the row's n_props label bytes.  16-byte stores when a row is whole 16-byte
 // units, else 4-byte, else single bytes.
 __global__ void __launch_bounds__(256)
-k_combine(const uint64_t *__restrict__ P, uint64_t p_stride, uint32_t n_wr, uint64_t n_traj, uint32_t n_props,
+k_combine(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile, uint64_t n_traj, uint32_t n_props,
           uint8_t *__restrict__ L)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const bool v16 = (n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(L) & 15u) == 0;
     const bool v4 = (n_props & 3u) == 0 && (reinterpret_cast<uintptr_t>(L) & 3u) == 0;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_traj; t += stride) {
-        uint64_t bits = 0;
-        uint32_t r = 0;
-        for (; r + 4 <= n_wr; r += 4)
-            bits |= P[(uint64_t)r * p_stride + t] | P[(uint64_t)(r + 1) * p_stride + t] |
-                    P[(uint64_t)(r + 2) * p_stride + t] | P[(uint64_t)(r + 3) * p_stride + t];
-        for (; r < n_wr; ++r) bits |= P[(uint64_t)r * p_stride + t];
+        const uint64_t bits = row_partials(P, rb_tile, t);
         uint8_t *dst = L + t * n_props;
         if (v16) {
             for (uint32_t p = 0; p < n_props; p += 16) {
@@ -379,15 +398,138 @@ unsigned grid_cap(uint64_t items, unsigned per_block, unsigned cap)
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr size_t kTileLds = (kRowBlock + (size_t)kTileWaves * kWordGroup * 256) * sizeof(uint64_t);
+// Cost of a task, in entries: one per entry plus this much per segment whose
+// table the task builds (a build is about a quarter of a round's work).
+constexpr double kSegCost = 16.0;
 
 }  // namespace
+
+// ---------------------------------------------------------------- host: tilings
+
+std::vector<uint32_t> tiles_per_block(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
+                                      uint32_t target)
+{
+    const size_t n_rb = rb_seg.size() - 1;
+    std::vector<uint32_t> k(n_rb, 1);
+    if (target <= n_rb) return k;
+    std::vector<double> cost(n_rb);
+    double total = 0;
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        cost[rb] = (double)(seg_start[rb_seg[rb + 1]] - seg_start[rb_seg[rb]]) +
+                   kSegCost * (double)(rb_seg[rb + 1] - rb_seg[rb]);
+        total += cost[rb];
+    }
+    if (total <= 0) return k;
+    uint64_t sum = 0;
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        k[rb] = std::max<uint32_t>(1, (uint32_t)std::floor(target * cost[rb] / total));
+        sum += k[rb];
+    }
+    // largest cost per tile gets the next tile; smallest gives one back
+    while (sum < target) {
+        size_t best = 0;
+        for (size_t rb = 1; rb < n_rb; ++rb)
+            if (cost[rb] / k[rb] > cost[best] / k[best]) best = rb;
+        ++k[best];
+        ++sum;
+    }
+    while (sum > target) {
+        size_t best = n_rb;
+        for (size_t rb = 0; rb < n_rb; ++rb)
+            if (k[rb] > 1 && (best == n_rb || cost[rb] / (k[rb] - 1) < cost[best] / (k[best] - 1))) best = rb;
+        if (best == n_rb) break;
+        --k[best];
+        --sum;
+    }
+    return k;
+}
+
+void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
+                 const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out)
+{
+    const size_t n_rb = rb_seg.size() - 1;
+    out->tasks.clear();
+    out->rounds.clear();
+    out->rb_tile.assign(n_rb + 1, 0);
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        out->rb_tile[rb + 1] = out->rb_tile[rb] + tiles_rb[rb];
+        const uint64_t s_lo = rb_seg[rb], s_hi = rb_seg[rb + 1];
+        const uint64_t E0 = seg_start[s_lo], E1 = seg_start[s_hi];
+        const uint64_t m = (uint64_t)tiles_rb[rb] * kTileWaves;
+        const double C = (double)(E1 - E0) + kSegCost * (double)(s_hi - s_lo);
+        // task boundaries at equal cost: cost(e) = (e - E0) + kSegCost * (segments started at or before e)
+        std::vector<uint64_t> bnd(m + 1, E1);
+        bnd[0] = E0;
+        uint64_t s = s_lo;
+        for (uint64_t q = 1; q < m; ++q) {
+            const double want = C * (double)q / (double)m;
+            while (s < s_hi && (double)(seg_start[s + 1] - E0) + kSegCost * (double)(s - s_lo + 1) < want) ++s;
+            uint64_t e = E1;
+            if (s < s_hi) {
+                const double at = want - (double)(seg_start[s] - E0) - kSegCost * (double)(s - s_lo + 1);
+                e = seg_start[s] + (uint64_t)std::max(0.0, std::floor(at));
+                e = std::min(e, seg_start[s + 1]);
+            }
+            bnd[q] = std::max(bnd[q - 1], std::min(e, E1));
+        }
+        // rounds of each task
+        uint64_t sp = s_lo;  // segment containing the current entry
+        for (uint64_t q = 0; q < m; ++q) {
+            const uint64_t lo = bnd[q], hi = bnd[q + 1];
+            SpTask t{lo, 0, (uint32_t)out->rounds.size()};
+            int64_t built = -1;
+            for (uint64_t c0 = lo; c0 < hi; c0 += 64) {
+                const uint64_t c1 = std::min(c0 + 64, hi);
+                while (seg_start[sp + 1] <= c0) ++sp;
+                uint64_t a = sp;
+                uint32_t lane_lo = 0;
+                for (;;) {
+                    const uint64_t end_a = seg_start[a + 1];
+                    const bool two = end_a < c1;  // the next segment starts inside the round
+                    const uint64_t b = two ? a + 1 : a;
+                    const uint64_t end_r = std::min(c1, seg_start[b + 1]);
+                    const uint32_t lane_hi = (uint32_t)(end_r - c0);
+                    const uint32_t cut = two ? (uint32_t)(end_a - c0) : 64u;
+                    uint32_t meta = lane_lo | lane_hi << 8 | cut << 16;
+                    if ((int64_t)a > built) {
+                        meta |= kMetaBuild0;
+                        built = (int64_t)a;
+                    }
+                    if (two && (int64_t)b > built) {
+                        meta |= kMetaBuild1;
+                        built = (int64_t)b;
+                    }
+                    if (a & 1) meta |= kMetaSlot0;  // slot of a segment = parity of its index
+                    out->rounds.push_back(SpRound{(uint32_t)(c0 - lo), seg_word[a], seg_word[b], meta});
+                    ++t.n_rounds;
+                    if (end_r >= c1) break;
+                    a = b + 1;  // starts at end_r
+                    lane_lo = lane_hi;
+                }
+            }
+            out->tasks.push_back(t);
+        }
+    }
+}
+
+SparseLayout::~SparseLayout()
+{
+    (void)hipFree(row);
+    (void)hipFree(val);
+    for (SpTiling &t : tilings) {
+        (void)hipFree(t.tasks);
+        (void)hipFree(t.rounds);
+        (void)hipFree(t.rb_tile);
+    }
+}
+
+void free_sparse(SparseLayout *sp) { delete sp; }
 
 hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, uint32_t n_tiles, hipStream_t s)
 {
     if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_label_tiles_batch<kTileWaves, kWordGroup>), dim3(n_tiles), dim3(64 * kTileWaves), kTileLds, s,
-                       d_groups, d_tiles);
+    hipLaunchKernelGGL(k_label_tiles_batch<kTileWaves>, dim3(n_tiles), dim3(64 * kTileWaves), kTileLds, s, d_groups,
+                       d_tiles);
     return hipGetLastError();
 }
 
@@ -396,6 +538,22 @@ hipError_t launch_combine_batch(const GroupDesc *d_groups, const CombineItem *d_
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_combine_batch, dim3(n_items), dim3(64), 0, s, d_groups, d_items);
     return hipGetLastError();
+}
+
+static lbl_status upload_tiling(const TilingHost &h, SpTiling *t, size_t *bytes)
+{
+    t->n_tiles = (uint32_t)(h.tasks.size() / kTileWaves);
+    t->n_rounds = h.rounds.size();
+    t->rb_tile_host = h.rb_tile;
+    LBL_HIP_TRY(hipMalloc(&t->tasks, h.tasks.size() * sizeof(SpTask)));
+    LBL_HIP_TRY(hipMemcpy(t->tasks, h.tasks.data(), h.tasks.size() * sizeof(SpTask), hipMemcpyHostToDevice));
+    LBL_HIP_TRY(hipMalloc(&t->rounds, std::max<size_t>(h.rounds.size(), 1) * sizeof(SpRound)));
+    if (!h.rounds.empty())
+        LBL_HIP_TRY(hipMemcpy(t->rounds, h.rounds.data(), h.rounds.size() * sizeof(SpRound), hipMemcpyHostToDevice));
+    LBL_HIP_TRY(hipMalloc(&t->rb_tile, h.rb_tile.size() * sizeof(uint32_t)));
+    LBL_HIP_TRY(hipMemcpy(t->rb_tile, h.rb_tile.data(), h.rb_tile.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    *bytes += h.tasks.size() * sizeof(SpTask) + h.rounds.size() * sizeof(SpRound) + h.rb_tile.size() * sizeof(uint32_t);
+    return LBL_OK;
 }
 
 lbl_status build_sparse(lbl_abs *a)
@@ -430,71 +588,95 @@ lbl_status build_sparse(lbl_abs *a)
                        d_ptr, d_row, d_val);
     LBL_HIP_TRY(hipGetLastError());
 
-    // 2. tile geometry: ~1024 tiles, at least kTileWaves * kWordGroup words per tile
-    SparseGeom g;
-    g.n_rb = (uint32_t)((a->n_traj + kRowBlock - 1) / kRowBlock);
-    const uint32_t min_words = kTileWaves * kWordGroup;
-    uint32_t n_wr = std::max<uint32_t>(1, (1024 + g.n_rb - 1) / g.n_rb);
-    n_wr = std::min<uint32_t>(n_wr, std::max<uint32_t>(1, W / min_words));
-    g.wr_words = (W + n_wr - 1) / n_wr;
-    g.n_wr = (W + g.wr_words - 1) / g.wr_words;
-
-    // 3. segment counts -> offsets (host scan) -> tiled copy
-    const uint64_t n_seg = (uint64_t)g.n_rb * W;
+    // 2. segment counts (every (rb, w), empty ones included) -> offsets (host scan) -> tiled copy
+    std::unique_ptr<SparseLayout> sp(new SparseLayout);
+    sp->n_rb = (uint32_t)((a->n_traj + kRowBlock - 1) / kRowBlock);
+    const uint64_t n_seg = (uint64_t)sp->n_rb * W;
     uint32_t *d_cnt = nullptr;
-    LBL_HIP_TRY(hipMalloc(&d_cnt, n_seg * sizeof(uint32_t)));
+    LBL_HIP_TRY(hipMalloc(&d_cnt, std::max<uint64_t>(n_seg, 1) * sizeof(uint32_t)));
     std::unique_ptr<uint32_t, decltype(&hipFree)> g_cnt(d_cnt, &hipFree);
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, W,
-                       g.n_rb, d_cnt);
+                       sp->n_rb, d_cnt);
     LBL_HIP_TRY(hipGetLastError());
     std::vector<uint32_t> cnt(n_seg);
     LBL_HIP_TRY(hipMemcpy(cnt.data(), d_cnt, n_seg * sizeof(uint32_t), hipMemcpyDeviceToHost));
     std::vector<uint64_t> seg(n_seg + 1, 0);
     for (uint64_t s = 0; s < n_seg; ++s) seg[s + 1] = seg[s] + cnt[s];
     LBL_REQUIRE(seg[n_seg] == nnz, "sparse layout: segment counts disagree with the word counts");
-    LBL_HIP_TRY(hipMalloc(&a->sp_seg, (n_seg + 1) * sizeof(uint64_t)));
-    LBL_HIP_TRY(hipMemcpy(a->sp_seg, seg.data(), (n_seg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
-    LBL_HIP_TRY(hipMalloc(&a->sp_row, std::max<uint64_t>(nnz, 1) * sizeof(uint16_t)));
-    LBL_HIP_TRY(hipMalloc(&a->sp_val, std::max<uint64_t>(nnz, 1) * sizeof(uint64_t)));
+    uint64_t *d_seg = nullptr;
+    LBL_HIP_TRY(hipMalloc(&d_seg, (n_seg + 1) * sizeof(uint64_t)));
+    std::unique_ptr<uint64_t, decltype(&hipFree)> g_seg(d_seg, &hipFree);
+    LBL_HIP_TRY(hipMemcpy(d_seg, seg.data(), (n_seg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+    LBL_HIP_TRY(hipMalloc(&sp->row, std::max<uint64_t>(nnz, 1) * sizeof(uint16_t)));
+    LBL_HIP_TRY(hipMalloc(&sp->val, std::max<uint64_t>(nnz, 1) * sizeof(uint64_t)));
     hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, d_val, W,
-                       g.n_rb, a->sp_seg, a->sp_row, a->sp_val);
+                       sp->n_rb, d_seg, sp->row, sp->val);
     LBL_HIP_TRY(hipGetLastError());
+    sp->nnz = nnz;
+
+    // 3. non-empty segments, and the tilings over them
+    std::vector<uint64_t> seg_start, rb_seg(sp->n_rb + 1, 0);
+    std::vector<uint32_t> seg_word;
+    for (uint32_t rb = 0; rb < sp->n_rb; ++rb) {
+        rb_seg[rb] = seg_word.size();
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint64_t s = (uint64_t)rb * W + w;
+            if (cnt[s] == 0) continue;
+            seg_start.push_back(seg[s]);
+            seg_word.push_back(w);
+        }
+    }
+    rb_seg[sp->n_rb] = seg_word.size();
+    seg_start.push_back(nnz);
+    sp->n_segments = seg_word.size();
+    // tile workgroups use more than 64 KB of LDS
+    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles<kTileWaves>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
+    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles_batch<kTileWaves>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
+    const uint32_t n_cu = (uint32_t)device_cu_count();
+    sp->tilings.resize(1 + kBatchTilings);
+    for (int i = 0; i <= kBatchTilings; ++i) {
+        std::vector<uint32_t> k = i == 0 ? tiles_per_block(seg_start, rb_seg, n_cu)
+                                         : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
+        TilingHost h;
+        make_tiling(seg_start, seg_word, rb_seg, k, &h);
+        lbl_status st = upload_tiling(h, &sp->tilings[i], &sp->round_bytes);
+        if (st != LBL_OK) return st;
+    }
     LBL_HIP_TRY(hipDeviceSynchronize());
-    a->sp_nnz = nnz;
-    a->sp_geom = g;
+    a->sp = sp.release();
     return LBL_OK;
 }
 
-size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups)
+size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)
 {
-    const SparseGeom &g = a->sp_geom;
     return up256((size_t)a->n_words * 64 * n_lane_groups * sizeof(uint64_t)) +
-           (size_t)n_lane_groups * g.n_wr * g.n_rb * kRowBlock * sizeof(uint64_t);
+           (size_t)n_lane_groups * a->sp->tilings[t].n_tiles * kRowBlock * sizeof(uint64_t);
 }
 
 lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s)
 {
-    LBL_REQUIRE(a->sp_seg != nullptr, "the abstraction has no sparse layout");
-    const SparseGeom &g = a->sp_geom;
+    LBL_REQUIRE(a->sp != nullptr, "the abstraction has no sparse layout");
+    const SparseLayout &sp = *a->sp;
+    const SpTiling &tl = sp.tilings[0];
     uint64_t *Oc = static_cast<uint64_t *>(ws);
     uint64_t *P = Oc + up256((size_t)a->n_words * 64 * sizeof(uint64_t)) / sizeof(uint64_t);
-    const uint64_t p_stride = (uint64_t)g.n_rb * kRowBlock;
-    void *sp = span_begin(s);
+    void *spn = span_begin(s);
     hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)(((uint64_t)a->n_words * 64 + 255) / 256)), dim3(256), 0, s, O,
                        n_props, a->d_word_cell, a->n_words, Oc);
     LBL_HIP_TRY(hipGetLastError());
-    span_end(sp, s, 0);
-    sp = span_begin(s);
-    hipLaunchKernelGGL((k_label_tiles<kTileWaves, kWordGroup>), dim3((unsigned)g.n_tiles()), dim3(64 * kTileWaves),
-                       kTileLds, s, a->sp_seg, a->sp_row, a->sp_val, Oc, (uint64_t)64, a->n_words, g.n_wr, g.wr_words,
-                       a->n_traj, std::max<uint64_t>(a->sp_nnz, 1) - 1, P, p_stride);
+    span_end(spn, s, 0);
+    spn = span_begin(s);
+    hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.tasks,
+                       tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Oc, P);
     LBL_HIP_TRY(hipGetLastError());
-    span_end(sp, s, 1);
-    sp = span_begin(s);
-    hipLaunchKernelGGL(k_combine, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, p_stride, g.n_wr,
-                       a->n_traj, n_props, L);
+    span_end(spn, s, 1);
+    spn = span_begin(s);
+    hipLaunchKernelGGL(k_combine, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile, a->n_traj,
+                       n_props, L);
     LBL_HIP_TRY(hipGetLastError());
-    span_end(sp, s, 3);
+    span_end(spn, s, 3);
     return LBL_OK;
 }
 

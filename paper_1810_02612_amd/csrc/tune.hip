@@ -67,13 +67,13 @@ bool kernel_from_name(const std::string &s, Kernel *k)
 Plan default_plan(const lbl_abs *a)
 {
     Plan p;
-    p.kernel = a->sp_seg ? Kernel::Sparse : Kernel::Bits;
+    p.kernel = a->sp ? Kernel::Sparse : Kernel::Bits;
     return p;
 }
 
 bool plan_usable(const lbl_abs *a, const Plan &p)
 {
-    return !(p.kernel == Kernel::MfmaI8 && !a->T_i8) && !(p.kernel == Kernel::Sparse && !a->sp_seg);
+    return !(p.kernel == Kernel::MfmaI8 && !a->T_i8) && !(p.kernel == Kernel::Sparse && !a->sp);
 }
 
 // Synthetic frame: every (cell, proposition) byte is 1 with probability
@@ -99,7 +99,7 @@ std::string plan_name(const Plan &p)
     if (p.kernel == Kernel::Bits)
         snprintf(buf, sizeof(buf), "bits(unroll=%d,waves=%d)", p.bits.unroll, p.bits.waves_per_block);
     else if (p.kernel == Kernel::Sparse)
-        snprintf(buf, sizeof(buf), "sparse(rows=%u,waves=%u,words=%u)", kRowBlock, kTileWaves, kWordGroup);
+        snprintf(buf, sizeof(buf), "sparse(rows=%u,waves=%u)", kRowBlock, kTileWaves);
     else
         snprintf(buf, sizeof(buf), "%s(m_tiles=%d,waves=%d)", kernel_name(p.kernel), p.mfma.m_tiles,
                  p.mfma.waves_per_block);
@@ -174,7 +174,7 @@ lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint
     const size_t l_bytes = (size_t)a->n_traj * n_props;
     // workspace large enough for every candidate plan
     size_t ws_bytes = (size_t)a->n_words * 64 * sizeof(uint64_t);
-    if (a->sp_seg) ws_bytes = std::max(ws_bytes, swm_workspace_bytes(a));
+    if (a->sp) ws_bytes = std::max(ws_bytes, swm_workspace_bytes(a));
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     uint8_t *buf = nullptr;
     LBL_HIP_TRY(hipMalloc(&buf, up(ws_bytes) + up(l_bytes) + up(o_bytes)));
@@ -190,7 +190,7 @@ lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint
         LBL_HIP_TRY(hipGetLastError());
     }
     std::vector<Plan> cands;
-    if (a->sp_seg) {
+    if (a->sp) {
         Plan p;
         p.kernel = Kernel::Sparse;
         cands.push_back(p);

@@ -55,7 +55,9 @@ class AbsInfo(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_uint64), ("nx", ctypes.c_uint32), ("ny", ctypes.c_uint32),
                 ("n_words", ctypes.c_uint32), ("row_stride", ctypes.c_uint32), ("bits_bytes", ctypes.c_uint64),
                 ("int8_bytes", ctypes.c_uint64), ("nonzero_words", ctypes.c_uint64), ("set_cells", ctypes.c_uint64),
-                ("sparse_entries", ctypes.c_uint64), ("sparse_bytes", ctypes.c_uint64)]
+                ("sparse_entries", ctypes.c_uint64), ("sparse_bytes", ctypes.c_uint64),
+                ("sparse_frame_bytes", ctypes.c_uint64), ("sparse_tiles", ctypes.c_uint32),
+                ("sparse_row_block", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):

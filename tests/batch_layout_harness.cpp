@@ -6,6 +6,7 @@
 // the host image.
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <map>
 #include <random>
 #include <set>
@@ -89,20 +90,22 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     // sparse plans: partial regions inside and disjoint, every tile once,
     // every row of every lane group combined once
     bool sparse = true;
-    for (const JobRef &j : jobs) sparse = sparse && j.a->sp_seg != nullptr;
+    for (const JobRef &j : jobs) sparse = sparse && j.a->sp != nullptr;
     CHECK(p.sparse == sparse);
     if (!p.sparse) return;
+    CHECK(p.tiling >= 1 && p.tiling <= kBatchTilings);
     std::vector<std::pair<const uint8_t *, const uint8_t *>> p_ranges;
-    std::set<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>> tiles;
+    std::set<std::tuple<uint32_t, uint32_t, uint32_t>> tiles;
     uint64_t want_tiles = 0;
     for (size_t g = 0; g < p.groups.size(); ++g) {
         const GroupDesc &d = gs[g];
+        const SpTiling &tl = p.group_abs[g]->sp->tilings[p.tiling];
+        CHECK(d.n_tiles == tl.n_tiles && d.sp_tasks == tl.tasks && d.sp_rounds == tl.rounds && d.sp_rb_tile == tl.rb_tile);
         CHECK(d.n_rb == (uint32_t)((d.n_traj + kRowBlock - 1) / kRowBlock));
-        CHECK(d.n_wr >= 1 && (uint64_t)d.n_wr * d.wr_words >= d.n_words && (d.n_wr - 1) * d.wr_words < d.n_words);
-        const size_t pb = (size_t)d.G64 * d.n_wr * d.n_rb * kRowBlock * sizeof(uint64_t);
+        const size_t pb = (size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t);
         CHECK(inside(d.P, pb));
         p_ranges.push_back({reinterpret_cast<const uint8_t *>(d.P), reinterpret_cast<const uint8_t *>(d.P) + pb});
-        want_tiles += (uint64_t)d.n_rb * d.n_wr * d.G64;
+        want_tiles += (uint64_t)d.n_tiles * d.G64;
     }
     for (size_t i = 0; i < p_ranges.size(); ++i) {
         CHECK(p_ranges[i].second <= ow_ranges.front().first || p_ranges[i].first >= ow_ranges.back().second);
@@ -114,8 +117,8 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     for (const TileItem &t : p.tiles) {
         CHECK(t.group < p.groups.size());
         const GroupDesc &d = p.groups[t.group];
-        CHECK(t.rb < d.n_rb && t.wr < d.n_wr && t.gi < d.G64);
-        tiles.insert(std::make_tuple(t.group, t.rb, t.wr, t.gi));
+        CHECK(t.tile < d.n_tiles && t.gi < d.G64);
+        tiles.insert(std::make_tuple(t.group, t.tile, t.gi));
     }
     CHECK(tiles.size() == p.tiles.size() && p.tiles.size() == want_tiles);
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> rows;
@@ -129,6 +132,148 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
             const uint64_t covered_rows = rows[std::make_pair((uint32_t)g, gi)];
             CHECK(covered_rows == p.groups[g].n_traj);
         }
+}
+
+// A fake sparse layout for an abstraction of `rows` rows: tilings with
+// 1, 2, 4, 8 tiles per row block (and a one-frame tiling), fake addresses.
+// Never freed (its destructor would release the fake addresses).
+static SparseLayout *fake_layout(uint64_t rows, uint64_t base)
+{
+    SparseLayout *sp = new SparseLayout;
+    sp->n_rb = (uint32_t)((rows + kRowBlock - 1) / kRowBlock);
+    sp->nnz = rows * 50;
+    sp->row = reinterpret_cast<uint16_t *>(base);
+    sp->val = reinterpret_cast<uint64_t *>(base + 0x10000000ull);
+    sp->tilings.resize(1 + kBatchTilings);
+    for (int i = 0; i <= kBatchTilings; ++i) {
+        SpTiling &t = sp->tilings[i];
+        t.n_tiles = i == 0 ? std::max<uint32_t>(sp->n_rb, 256) : sp->n_rb << (i - 1);
+        t.tasks = reinterpret_cast<SpTask *>(base + 0x20000000ull + 0x1000000ull * i);
+        t.rounds = reinterpret_cast<SpRound *>(base + 0x30000000ull + 0x1000000ull * i);
+        t.rb_tile = reinterpret_cast<uint32_t *>(base + 0x40000000ull + 0x1000000ull * i);
+    }
+    return sp;
+}
+
+// ---------------------------------------------------------------- tilings
+
+// Random non-empty segments over n_rb row blocks of W words: returns the
+// segment starts (with the end sentinel), words and first segment of each
+// block.  mode 0: typical sizes; 1: many tiny segments; 2: few huge ones;
+// 3: some empty row blocks.
+static void random_segments(std::mt19937 &rng, uint32_t n_rb, uint32_t W, int mode, std::vector<uint64_t> *start,
+                            std::vector<uint32_t> *word, std::vector<uint64_t> *rb_seg)
+{
+    start->clear();
+    word->clear();
+    rb_seg->assign(n_rb + 1, 0);
+    uint64_t e = 0;
+    for (uint32_t rb = 0; rb < n_rb; ++rb) {
+        (*rb_seg)[rb] = word->size();
+        if (mode == 3 && rng() % 3 == 0) continue;
+        for (uint32_t w = 0; w < W; ++w) {
+            uint32_t n = 0;
+            if (mode == 0) n = rng() % 4 == 0 ? 0 : 1 + rng() % 120;
+            if (mode == 1) n = rng() % 2 == 0 ? 0 : 1 + rng() % 5;
+            if (mode == 2) n = rng() % 16 == 0 ? 200 + rng() % 3000 : 0;
+            if (mode == 3) n = rng() % 3 == 0 ? 0 : 1 + rng() % 90;
+            if (n == 0) continue;
+            start->push_back(e);
+            word->push_back(w);
+            e += n;
+        }
+    }
+    (*rb_seg)[n_rb] = word->size();
+    start->push_back(e);
+}
+
+// Walk the tiling as the tile kernel does and check that every entry is
+// taken by exactly one active lane, reading the table of its own segment's
+// word, built before use.
+static void check_tiling(const std::vector<uint64_t> &start, const std::vector<uint32_t> &word,
+                         const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &k)
+{
+    TilingHost h;
+    make_tiling(start, word, rb_seg, k, &h);
+    const size_t n_rb = rb_seg.size() - 1;
+    uint64_t n_tiles = 0;
+    for (uint32_t x : k) n_tiles += x;
+    CHECK(h.tasks.size() == n_tiles * kTileWaves);
+    CHECK(h.rb_tile.size() == n_rb + 1 && h.rb_tile[0] == 0 && h.rb_tile[n_rb] == n_tiles);
+    const uint64_t nnz = start.back();
+    std::vector<uint8_t> seen(nnz, 0);
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        CHECK(h.rb_tile[rb + 1] - h.rb_tile[rb] == k[rb]);
+        const uint64_t E0 = start[rb_seg[rb]], E1 = start[rb_seg[rb + 1]];
+        uint64_t next = E0;  // tasks of the block cover [E0, E1) in order
+        for (uint64_t t = h.rb_tile[rb]; t < h.rb_tile[rb + 1]; ++t)
+            for (uint32_t wv = 0; wv < kTileWaves; ++wv) {
+                const SpTask &tk = h.tasks[t * kTileWaves + wv];
+                CHECK(tk.lo == next);
+                int64_t slot_word[2] = {-1, -1};
+                uint64_t hi = tk.lo;
+                for (uint32_t i = 0; i < tk.n_rounds; ++i) {
+                    CHECK((uint64_t)tk.round0 + i < h.rounds.size());
+                    const SpRound &r = h.rounds[tk.round0 + i];
+                    CHECK(r.e_off % 64 == 0);
+                    const uint32_t lane_lo = r.meta & 0xFF, lane_hi = (r.meta >> 8) & 0xFF, cut = (r.meta >> 16) & 0xFF;
+                    CHECK(lane_lo < lane_hi && lane_hi <= 64 && cut <= 64 && (r.meta >> 27) == 0);
+                    const uint32_t s0 = (r.meta & kMetaSlot0) ? 1 : 0;
+                    if (r.meta & kMetaBuild0) slot_word[s0] = r.word0;
+                    if (r.meta & kMetaBuild1) slot_word[s0 ^ 1] = r.word1;
+                    for (uint32_t l = lane_lo; l < lane_hi; ++l) {
+                        const uint64_t e = tk.lo + r.e_off + l;
+                        CHECK(e < E1);
+                        if (e >= E1) continue;
+                        ++seen[e];
+                        // segment of e
+                        const uint64_t s = std::upper_bound(start.begin(), start.end(), e) - start.begin() - 1;
+                        CHECK(s >= rb_seg[rb] && s < rb_seg[rb + 1]);
+                        const uint32_t slot = s0 ^ (l >= cut ? 1 : 0);
+                        CHECK(slot_word[slot] == (int64_t)word[s]);
+                        CHECK(slot == (s & 1));
+                        hi = std::max(hi, e + 1);
+                    }
+                }
+                next = hi;
+            }
+        CHECK(next == E1);
+    }
+    for (uint64_t e = 0; e < nnz; ++e) CHECK(seen[e] == 1);
+}
+
+static void check_tilings()
+{
+    std::mt19937 rng(11);
+    std::vector<uint64_t> start, rb_seg;
+    std::vector<uint32_t> word;
+    for (int mode = 0; mode < 4; ++mode)
+        for (int trial = 0; trial < 3; ++trial) {
+            const uint32_t n_rb = 1 + rng() % 5, W = 16 + rng() % 300;
+            random_segments(rng, n_rb, W, mode, &start, &word, &rb_seg);
+            for (uint32_t target : {1u, 3u, 7u, 40u}) {
+                const std::vector<uint32_t> k = tiles_per_block(start, rb_seg, target);
+                uint64_t sum = 0;
+                for (uint32_t x : k) {
+                    CHECK(x >= 1);
+                    sum += x;
+                }
+                // a layout without entries keeps one tile per block
+                CHECK(sum == (start.back() == 0 ? n_rb : std::max<uint64_t>(target, n_rb)));
+                check_tiling(start, word, rb_seg, k);
+            }
+            check_tiling(start, word, rb_seg, std::vector<uint32_t>(n_rb, 2));
+        }
+    // balance: tasks of equal cost within a block (typical sizes, one block)
+    random_segments(rng, 1, 4096, 0, &start, &word, &rb_seg);
+    TilingHost h;
+    make_tiling(start, word, rb_seg, std::vector<uint32_t>(1, 16), &h);
+    uint32_t mx = 0, mn = ~0u;
+    for (const SpTask &t : h.tasks) {
+        mx = std::max(mx, t.n_rounds);
+        mn = std::min(mn, t.n_rounds);
+    }
+    CHECK(mx <= mn + mn / 5 + 4);
 }
 
 int main()
@@ -166,13 +311,7 @@ int main()
         }
     check_case(abss, jobs, BatchTile{4, 16, 32});
     // the same batches with the sparse layout present on every abstraction
-    for (int i = 0; i < 6; ++i) {
-        abss[i].sp_seg = reinterpret_cast<uint64_t *>(0x300000000000ull + 0x10000000ull * i);
-        abss[i].sp_row = reinterpret_cast<uint16_t *>(0x310000000000ull + 0x10000000ull * i);
-        abss[i].sp_val = reinterpret_cast<uint64_t *>(0x320000000000ull + 0x10000000ull * i);
-        abss[i].sp_nnz = rows[i] * 50;
-        abss[i].sp_geom.n_rb = (uint32_t)((rows[i] + kRowBlock - 1) / kRowBlock);
-    }
+    for (int i = 0; i < 6; ++i) abss[i].sp = fake_layout(rows[i], 0x300000000000ull + 0x100000000ull * i);
     check_case(abss, jobs, BatchTile{});
     for (int trial = 0; trial < 10; ++trial) {
         std::vector<JobRef> js;
@@ -185,9 +324,11 @@ int main()
         check_case(abss, js, BatchTile{});
     }
     // a batch mixing an abstraction without the sparse layout is planned bitpacked
-    abss[2].sp_seg = nullptr;
+    SparseLayout *keep = abss[2].sp;
+    abss[2].sp = nullptr;
     check_case(abss, jobs, BatchTile{});
-    abss[2].sp_seg = reinterpret_cast<uint64_t *>(0x300000000000ull + 0x20000000ull);
+    abss[2].sp = keep;
+    check_tilings();
     // invalid jobs are rejected without touching anything
     BatchPlan p;
     JobRef bad{&abss[0], nullptr, 8, fake};
