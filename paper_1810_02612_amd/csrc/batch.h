@@ -22,9 +22,9 @@ struct LaneDesc {
 struct GroupDesc {
     const uint64_t *T;
     const uint32_t *word_cell;
-    uint64_t *Ow;             // [n_words][G64][64] packed masks: bitpacked plans index the
-                              // last axis by column (64 cells per mask), sparse plans by
-                              // cell (64 columns per mask)
+    uint64_t *Ow;             // bitpacked plans: [n_words][G64][64] masks, one per column
+                              // (64 cells each); sparse plans: [n_words][G64][256] nibble
+                              // tables
     const LaneDesc *lanes;    // [G64][64]
     uint64_t n_traj;
     uint32_t row_stride;

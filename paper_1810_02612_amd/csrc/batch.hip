@@ -17,6 +17,7 @@
 #include "batch.h"
 #include "profile.h"
 #include "sparse.h"
+#include "tables.h"
 
 namespace lbl {
 
@@ -37,8 +38,8 @@ __global__ void k_zero(uint32_t *counter) { *counter = 0u; }
 // One wavefront per (group, word, lane group): lane l packs the 64 cells of
 // the word for the proposition column that lane (gi, l) stands for.  With
 // PER_CELL the 64 x 64 bit block is transposed across the wavefront (64
-// ballots) so that lane b stores the mask of columns met by cell b, the
-// layout the sparse kernels read.
+// ballots) so that lane b holds the mask of columns met by cell b, and the
+// word's nibble tables (the layout the sparse kernels read) are written.
 template <bool PER_CELL>
 __global__ void __launch_bounds__(256)
 k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
@@ -66,9 +67,10 @@ k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ 
                 const uint64_t col = __ballot((m >> b) & 1ull);  // bit l: column l meets cell b
                 t = lane == b ? col : t;
             }
-            m = t;
+            write_tables(t, g.Ow + ((uint64_t)w * g.G64 + gi) * 256, lane);
+        } else {
+            g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
         }
-        g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
     }
 }
 
@@ -225,7 +227,9 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
                 p.pairs += a->n_traj * r.n_props;
             }
             p.ow_off.push_back(p.ow_bytes);
-            p.ow_bytes += up256((size_t)a->n_words * g.G64 * 64 * sizeof(uint64_t));
+            // bitpacked plans: masks [w][G64][64 columns]; sparse plans:
+            // nibble tables [w][G64][256]
+            p.ow_bytes += up256((size_t)a->n_words * g.G64 * (p.sparse ? 256 : 64) * sizeof(uint64_t));
             p.pack_units += (uint64_t)a->n_words * g.G64;
             p.max_g64 = std::max(p.max_g64, g.G64);
             p.groups.push_back(g);

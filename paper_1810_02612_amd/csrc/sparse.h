@@ -16,8 +16,15 @@ constexpr uint32_t kTileWaves = 16;
 // Nibble tables a wavefront holds at once (a round touches at most two
 // segments).
 constexpr uint32_t kRing = 2;
+// A nibble table is 16 rows (nibble position) of 16 entries (nibble value),
+// each row padded by one entry: the 64 lanes of a table build then write to
+// distinct banks, and the second table of a wavefront starts half a bank
+// row after the first, so lookups into the two tables in one instruction do
+// not collide.
+constexpr uint32_t kTabRow = 17;
+constexpr uint32_t kTabWords = 16 * kTabRow;
 // LDS of a tile workgroup: accumulators + every wavefront's tables.
-constexpr size_t kTileLds = ((size_t)kRowBlock + (size_t)kTileWaves * kRing * 256) * sizeof(uint64_t);
+constexpr size_t kTileLds = ((size_t)kRowBlock + (size_t)kTileWaves * kRing * kTabWords) * sizeof(uint64_t);
 
 // One wavefront's share of a tile: consecutive entries lo .. of one row
 // block, processed as rounds [round0, round0 + n_rounds).
@@ -28,11 +35,13 @@ struct SpTask {
 };
 
 // One round: up to 64 consecutive entries, lane l taking entry
-// task.lo + e_off + l, each lane in one of two segments (words).
+// task.lo + e_off + l, each lane in one of two segments (words).  A round
+// builds at most one table slot: the first segment's (build0) or the
+// second's (build1), from the nibble tables of word tword.
 struct SpRound {
     uint32_t e_off;  // multiple of 64
-    uint32_t word0;  // word of the first segment
-    uint32_t word1;  // word of the second segment (word0 when unused)
+    uint32_t tword;  // word whose tables the round copies (the last built word if none)
+    uint32_t pad;
     uint32_t meta;   // lane_lo | lane_hi << 8 | cut << 16 | build0 << 24 | build1 << 25 | slot0 << 26
 };
 constexpr uint32_t kMetaBuild0 = 1u << 24, kMetaBuild1 = 1u << 25, kMetaSlot0 = 1u << 26;
@@ -78,7 +87,8 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
 // segment list (exposed for host tests).  seg_start[s] .. seg_start[s + 1]
 // are the entries of segment s, seg_word[s] its word, rb_seg[rb] ..
 // rb_seg[rb + 1] the segments of row block rb.  tiles_rb[rb] >= 1 tiles per
-// row block.
+// row block; the block's tasks start at 64-entry chunk boundaries and have
+// equal cost (rounds, plus a charge per table copy) as the block is walked.
 struct TilingHost {
     std::vector<SpTask> tasks;
     std::vector<SpRound> rounds;
@@ -86,8 +96,10 @@ struct TilingHost {
 };
 void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
                  const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out);
-// Tiles per row block for about `target` tiles of equal cost in total.
-std::vector<uint32_t> tiles_per_block(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
-                                      uint32_t target);
+// Cost of walking each row block's entries in rounds.
+std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg);
+// Tiles per row block (at least one each) for `target` tiles in total of
+// about equal cost.
+std::vector<uint32_t> tiles_per_block(const std::vector<double> &cost, uint32_t target);
 
 }  // namespace lbl

@@ -18,17 +18,18 @@
 // second segment, and which of its segments' tables must be built first.
 //
 // Per frame:
-//   k_pack_cells   O -> Oc[w][b]: 64-bit mask of the propositions that cell
-//                  b of word w meets (one lane per cell).
-//   k_label_tiles  one workgroup per tile.  A wavefront keeps the 16 x 16
-//                  nibble tables of two segments in LDS (entry [n][v] = OR
-//                  of Oc over the cells 4n + b with bit b of v set), building
-//                  a segment's table when a round first reaches it; every
-//                  active lane ORs the 16 table entries selected by the
-//                  nibbles of its word value (the labels of that (row, word)
-//                  pair for up to 64 propositions) into the tile's per-row
-//                  accumulators with an LDS atomic.  The accumulators are
-//                  written once per tile as its partial labels.
+//   k_pack_tables  O -> the nibble tables of every word: entry [n][v] is the
+//                  OR of the proposition masks of the cells 4n + b with bit
+//                  b of v set (16 x 16 uint64 per word, one wavefront per
+//                  word).
+//   k_label_tiles  one workgroup per tile.  A wavefront keeps two segments'
+//                  tables in LDS, copying a segment's tables in when a round
+//                  first reaches it (at most one copy per round); every
+//                  active lane ORs the 16 entries selected by the nibbles of
+//                  its word value (the labels of that (row, word) pair for up
+//                  to 64 propositions) into the tile's per-row accumulators
+//                  with an LDS atomic.  The accumulators are written once per
+//                  tile as its partial labels.
 //   k_combine      OR of a row's partials over the tiles of its row block ->
 //                  the caller's L bytes (0/1).
 // OR is idempotent and commutative, so neither the order of the LDS atomics
@@ -39,6 +40,7 @@
 #include "batch.h"
 #include "profile.h"
 #include "sparse.h"
+#include "tables.h"
 
 namespace lbl {
 
@@ -153,13 +155,14 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
     return ((h >> 7) | (h >> 14) | (h >> 21) | (h >> 28)) & 0xFu;
 }
 
-// One lane per cell: Oc[w * 64 + b] = propositions met by cell (w, b).
+// One wavefront per word, one lane per cell: the mask of the propositions
+// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].
 __global__ void __launch_bounds__(256)
-k_pack_cells(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell,
-             uint32_t n_words, uint64_t *__restrict__ Oc)
+k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell,
+              uint32_t n_words, uint64_t *__restrict__ Tg)
 {
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // w * 64 + b
-    if (idx >= (uint64_t)n_words * 64) return;
+    if (idx >= (uint64_t)n_words * 64) return;  // whole wavefronts (n_words * 64 is a multiple of 64)
     const uint8_t *src = O + (uint64_t)word_cell[idx] * n_props;
     uint64_t m = 0;
     if ((n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(O) & 15u) == 0) {
@@ -171,43 +174,65 @@ k_pack_cells(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__
     } else {
         for (uint32_t p = 0; p < n_props; ++p) m |= (uint64_t)(src[p] != 0) << p;
     }
-    Oc[idx] = m;
+    write_tables(m, Tg + (idx >> 6) * 256, threadIdx.x & 63);
 }
 
 
-// Value of lane C of each group of four lanes (DPP quad permutation).
-template <int C>
-__device__ __forceinline__ uint64_t quad_bcast(uint64_t v)
+// base + byte K of bytes, in one instruction (the byte is selected as an
+// operand, not extracted first).
+template <int K>
+__device__ __forceinline__ uint32_t add_byte(uint32_t base, uint32_t bytes)
 {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, C * 0x55, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), C * 0x55, 0xF, 0xF, false);
-    return ((uint64_t)hi << 32) | lo;
+    uint32_t r;
+    if constexpr (K == 0)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:DWORD"
+            : "=v"(r) : "v"(bytes), "v"(base));
+    else if constexpr (K == 1)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:DWORD"
+            : "=v"(r) : "v"(bytes), "v"(base));
+    else if constexpr (K == 2)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2 src1_sel:DWORD"
+            : "=v"(r) : "v"(bytes), "v"(base));
+    else
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_3 src1_sel:DWORD"
+            : "=v"(r) : "v"(bytes), "v"(base));
+    return r;
 }
 
-// Nibble tables of one word into t[16][16]; lane l holds the mask of cell l
-// of the word.  The four lanes of nibble n (cells 4n .. 4n + 3) share their
-// masks; lane 4n + j writes entries [n][j + 4m], m = 0..3.  Every lane of
-// the wavefront must be active.
-__device__ __forceinline__ void build_tables(uint64_t cell, uint64_t *t, uint32_t lane)
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+
+// Entry of table row q at LDS byte address addr + q * kTabRow * 8.
+__device__ __forceinline__ uint64_t lds_entry(uint32_t addr, int q)
 {
-    const uint64_t o0 = quad_bcast<0>(cell), o1 = quad_bcast<1>(cell);
-    const uint64_t o2 = quad_bcast<2>(cell), o3 = quad_bcast<3>(cell);
-    const uint32_t j = lane & 3u;
-    const uint64_t lo = ((j & 1u) ? o0 : 0ull) | ((j & 2u) ? o1 : 0ull);
-    uint64_t *e = t + (lane >> 2) * 16 + j;
-    e[0] = lo;
-    e[4] = lo | o2;
-    e[8] = lo | o3;
-    e[12] = lo | o2 | o3;
+    return *reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(addr + q * kTabRow * 8));
+}
+
+// LDS byte address of p.
+__device__ __forceinline__ uint32_t lds_addr(const uint64_t *p)
+{
+    return (uint32_t)reinterpret_cast<uintptr_t>((lds_u64 *)p);
+}
+
+// Copy of one word's nibble tables (as written by write_tables) into an LDS
+// table slot whose rows are kTabRow entries apart; lane l holds entries
+// 4l .. 4l + 3 (row l / 4).
+__device__ __forceinline__ void copy_tables(const ulonglong2 (&v)[2], uint64_t *t, uint32_t lane)
+{
+    uint64_t *e = t + (lane >> 2) * kTabRow + (lane & 3u) * 4;
+    e[0] = v[0].x;
+    e[1] = v[0].y;
+    e[2] = v[1].x;
+    e[3] = v[1].y;
 }
 
 // One tile: its wavefronts walk their tasks, OR-ing labels into the row
 // block's accumulators, then the accumulators become the tile's partials
-// Pt[0 .. kRowBlock).  Oc + w * oc_stride + b is the mask of cell b of word w.
+// Pt[0 .. kRowBlock).  Tg + w * tg_stride holds the 256 nibble-table entries
+// of word w.
 template <int WAVES>
 __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds,
                                           const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
-                                          uint64_t max_entry, const uint64_t *__restrict__ Oc, uint64_t oc_stride,
+                                          uint64_t max_entry, const uint64_t *__restrict__ Tg, uint64_t tg_stride,
                                           uint64_t tile, uint64_t *__restrict__ Pt, uint64_t *lds)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -215,7 +240,7 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
     // scalars and the per-round branches scalar branches
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t *acc = lds;                                  // kRowBlock accumulators
-    uint64_t *tab = lds + kRowBlock + wave * (kRing * 256);  // this wavefront's two tables
+    uint64_t *tab = lds + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
     for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
         reinterpret_cast<ulonglong2 *>(acc)[i] = make_ulonglong2(0ull, 0ull);
     __syncthreads();
@@ -226,9 +251,9 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
 
         struct Stage {
             uint32_t e_off, meta;
-            uint64_t x;       // this lane's word value
-            uint32_t r;       // its local row
-            uint64_t c0, c1;  // this lane's cell of each segment's word
+            uint64_t x;        // this lane's word value
+            uint32_t r;        // its local row
+            ulonglong2 tb[2];  // this lane's 32 bytes of the table the round builds
         };
         // Round records are read with scalar loads one round ahead of use.
         // Every vector load is unconditional at a clamped, in-bounds address
@@ -243,48 +268,61 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
             const uint64_t e = min(tk.lo + rec.e_off + lane, max_entry);
             st.x = sp_val[e];
             st.r = sp_row[e];
-            st.c0 = Oc[(uint64_t)rec.word0 * oc_stride + lane];
-            st.c1 = Oc[(uint64_t)rec.word1 * oc_stride + lane];
+            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)rec.tword * tg_stride) + 2 * lane;
+            st.tb[0] = src[0];
+            st.tb[1] = src[1];
         };
 
         auto process = [&](const Stage &st) {
             const uint32_t meta = st.meta;
             const uint32_t s0 = (meta & kMetaSlot0) ? 1u : 0u;
-            if (meta & kMetaBuild0) build_tables(st.c0, tab + s0 * 256, lane);
-            if (meta & kMetaBuild1) build_tables(st.c1, tab + (s0 ^ 1u) * 256, lane);
+            if (meta & (kMetaBuild0 | kMetaBuild1))
+                copy_tables(st.tb, tab + (s0 ^ ((meta & kMetaBuild1) ? 1u : 0u)) * kTabWords, lane);
             // LDS instructions of a wavefront complete in issue order, so the
             // lookups below see the whole table; the barrier only stops the
             // compiler from moving LDS accesses across this point.
             __builtin_amdgcn_wave_barrier();
             const uint32_t lane_lo = meta & 0xFFu, lane_hi = (meta >> 8) & 0xFFu, cut = (meta >> 16) & 0xFFu;
             if (lane >= lane_lo && lane < lane_hi) {
-                const uint64_t *t = tab + (s0 ^ (lane >= cut ? 1u : 0u)) * 256;
+                const uint64_t *t = tab + (s0 ^ (lane >= cut ? 1u : 0u)) * kTabWords;
+                // byte k of ev[h] (od[h]) is 8 x nibble 2k (2k + 1) of half h of
+                // the word value: the byte offset of its entry in the table row
                 const uint32_t lo = (uint32_t)st.x, hi = (uint32_t)(st.x >> 32);
+                const uint32_t ev[2] = {(lo << 3) & 0x78787878u, (hi << 3) & 0x78787878u};
+                const uint32_t od[2] = {(lo >> 1) & 0x78787878u, (hi >> 1) & 0x78787878u};
+                const uint32_t tb = lds_addr(t);
                 uint64_t a = 0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) a |= t[q * 16 + ((lo >> (4 * q)) & 0xFu)];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) a |= t[(q + 8) * 16 + ((hi >> (4 * q)) & 0xFu)];
+                for (int h = 0; h < 2; ++h) {
+                    a |= lds_entry(add_byte<0>(tb, ev[h]), 8 * h + 0) | lds_entry(add_byte<0>(tb, od[h]), 8 * h + 1);
+                    a |= lds_entry(add_byte<1>(tb, ev[h]), 8 * h + 2) | lds_entry(add_byte<1>(tb, od[h]), 8 * h + 3);
+                    a |= lds_entry(add_byte<2>(tb, ev[h]), 8 * h + 4) | lds_entry(add_byte<2>(tb, od[h]), 8 * h + 5);
+                    a |= lds_entry(add_byte<3>(tb, ev[h]), 8 * h + 6) | lds_entry(add_byte<3>(tb, od[h]), 8 * h + 7);
+                }
                 if (a) __hip_atomic_fetch_or(acc + st.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             __builtin_amdgcn_wave_barrier();  // later builds overwrite these tables
-            // the cell masks count as used here even when no table was built,
-            // so that their registers are not reused while their loads are in
-            // flight (which would make the next fetch wait for every load)
-            asm volatile("" ::"v"(st.c0), "v"(st.c1));
+            // the table data counts as used here even when no table was
+            // built, so that its registers are not reused while its loads are
+            // in flight (which would make the next fetch wait for every load)
+            asm volatile("" ::"v"(st.tb[0].x), "v"(st.tb[0].y), "v"(st.tb[1].x), "v"(st.tb[1].y));
         };
 
-        // ping-pong between two rounds so that one round's loads are in
-        // flight while the other is processed.  With n odd the last round is
-        // processed twice (fetch clamps to it), which changes nothing: its
-        // tables are rebuilt with the same contents and OR is idempotent.
-        Stage A, B;
+        // three rounds in rotation: while one is processed the loads of the
+        // next two are in flight.  When n is not a multiple of three the last
+        // round is processed again (fetch clamps to it), which changes
+        // nothing: its tables are rebuilt with the same contents and OR is
+        // idempotent.
+        Stage A, B, C;
         fetch(A, 0);
-        for (uint32_t i = 0; i < n; i += 2) {
-            fetch(B, i + 1);
+        fetch(B, 1);
+        for (uint32_t i = 0; i < n; i += 3) {
+            fetch(C, i + 2);
             process(A);
-            fetch(A, i + 2);
+            fetch(A, i + 3);
             process(B);
+            fetch(B, i + 4);
+            process(C);
         }
     }
     __syncthreads();
@@ -296,16 +334,16 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
 template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 k_label_tiles(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, uint64_t max_entry, const uint64_t *__restrict__ Oc,
+              const uint64_t *__restrict__ sp_val, uint64_t max_entry, const uint64_t *__restrict__ Tg,
               uint64_t *__restrict__ P)
 {
     extern __shared__ uint64_t lds[];
-    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Oc, 64, blockIdx.x, P + (uint64_t)blockIdx.x * kRowBlock,
+    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Tg, 256, blockIdx.x, P + (uint64_t)blockIdx.x * kRowBlock,
                      lds);
 }
 
-// One workgroup per (pass, tile, lane group) of a batch.  The pass's cell
-// masks are [w][G64][64] (cell-indexed), its partials [G64][n_tiles][kRowBlock].
+// One workgroup per (pass, tile, lane group) of a batch.  The pass's nibble
+// tables are [w][G64][256], its partials [G64][n_tiles][kRowBlock].
 template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items)
@@ -313,8 +351,8 @@ k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__rest
     extern __shared__ uint64_t lds[];
     const TileItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.max_entry, g.Ow + (uint64_t)it.gi * 64,
-                     (uint64_t)g.G64 * 64, it.tile,
+    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.max_entry, g.Ow + (uint64_t)it.gi * 256,
+                     (uint64_t)g.G64 * 256, it.tile,
                      g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
 }
 
@@ -398,27 +436,84 @@ unsigned grid_cap(uint64_t items, unsigned per_block, unsigned cap)
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Cost of a task, in entries: one per entry plus this much per segment whose
-// table the task builds (a build is about a quarter of a round's work).
-constexpr double kSegCost = 16.0;
+// Cost of a round, in rounds: one, plus this much when it copies a table in.
+constexpr double kBuildCost = 0.25;
+
+
+
+// The rounds of entries [lo, hi) of one row block as one wavefront walks them
+// with empty tables at the start: 64 entries per chunk from lo, at most two
+// segments and one table copy per round.  sp: a segment at or before the one
+// holding lo (advanced in place).  emit(c0, lane_lo, lane_hi, cut, a, build):
+// the round's chunk start, lane range, first lane of the second segment (64
+// if none), first segment, and -1 / 0 / 1 for no copy / copy of segment a /
+// copy of segment a + 1.
+template <class Emit>
+void walk_rounds(const std::vector<uint64_t> &seg_start, uint64_t lo, uint64_t hi, uint64_t &sp, Emit emit)
+{
+    int64_t built = -1;
+    for (uint64_t c0 = lo; c0 < hi; c0 += 64) {
+        const uint64_t c1 = std::min(c0 + 64, hi);
+        while (seg_start[sp + 1] <= c0) ++sp;
+        uint64_t a = sp;
+        uint32_t lane_lo = 0;
+        for (;;) {
+            const uint64_t end_a = seg_start[a + 1];
+            const bool two = end_a < c1;  // the next segment starts inside the round
+            const bool new_a = (int64_t)a > built, new_b = two && (int64_t)a + 1 > built;
+            if (new_a && new_b) {
+                // one table per round: the first segment's lanes alone
+                emit(c0, lane_lo, (uint32_t)(end_a - c0), 64u, a, 0);
+                built = (int64_t)a;
+                lane_lo = (uint32_t)(end_a - c0);
+                ++a;
+                continue;
+            }
+            const uint64_t b = two ? a + 1 : a;
+            const uint64_t end_r = std::min(c1, seg_start[b + 1]);
+            const uint32_t lane_hi = (uint32_t)(end_r - c0);
+            const uint32_t cut = two ? (uint32_t)(end_a - c0) : 64u;
+            const int build = new_a ? 0 : (new_b ? 1 : -1);
+            emit(c0, lane_lo, lane_hi, cut, a, build);
+            if (build >= 0) built = (int64_t)a + build;
+            if (end_r >= c1) break;
+            a = b + 1;  // starts at end_r
+            lane_lo = lane_hi;
+        }
+    }
+}
+
+// Cost of every 64-entry chunk of row block rb walked as one task.
+std::vector<double> chunk_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg, size_t rb)
+{
+    const uint64_t E0 = seg_start[rb_seg[rb]], E1 = seg_start[rb_seg[rb + 1]];
+    std::vector<double> c((E1 - E0 + 63) / 64, 0.0);
+    uint64_t sp = rb_seg[rb];
+    walk_rounds(seg_start, E0, E1, sp, [&](uint64_t c0, uint32_t, uint32_t, uint32_t, uint64_t, int build) {
+        c[(c0 - E0) / 64] += 1.0 + (build >= 0 ? kBuildCost : 0.0);
+    });
+    return c;
+}
 
 }  // namespace
 
 // ---------------------------------------------------------------- host: tilings
 
-std::vector<uint32_t> tiles_per_block(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
-                                      uint32_t target)
+std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg)
 {
-    const size_t n_rb = rb_seg.size() - 1;
+    std::vector<double> out(rb_seg.size() - 1, 0.0);
+    for (size_t rb = 0; rb + 1 < rb_seg.size(); ++rb)
+        for (double x : chunk_costs(seg_start, rb_seg, rb)) out[rb] += x;
+    return out;
+}
+
+std::vector<uint32_t> tiles_per_block(const std::vector<double> &cost, uint32_t target)
+{
+    const size_t n_rb = cost.size();
     std::vector<uint32_t> k(n_rb, 1);
     if (target <= n_rb) return k;
-    std::vector<double> cost(n_rb);
     double total = 0;
-    for (size_t rb = 0; rb < n_rb; ++rb) {
-        cost[rb] = (double)(seg_start[rb_seg[rb + 1]] - seg_start[rb_seg[rb]]) +
-                   kSegCost * (double)(rb_seg[rb + 1] - rb_seg[rb]);
-        total += cost[rb];
-    }
+    for (double c : cost) total += c;
     if (total <= 0) return k;
     uint64_t sum = 0;
     for (size_t rb = 0; rb < n_rb; ++rb) {
@@ -456,57 +551,39 @@ void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint3
         const uint64_t s_lo = rb_seg[rb], s_hi = rb_seg[rb + 1];
         const uint64_t E0 = seg_start[s_lo], E1 = seg_start[s_hi];
         const uint64_t m = (uint64_t)tiles_rb[rb] * kTileWaves;
-        const double C = (double)(E1 - E0) + kSegCost * (double)(s_hi - s_lo);
-        // task boundaries at equal cost: cost(e) = (e - E0) + kSegCost * (segments started at or before e)
+        // task boundaries at chunk starts, at equal cost of the rounds walked
+        // over the whole block
+        const std::vector<double> cc = chunk_costs(seg_start, rb_seg, rb);
+        double C = 0;
+        for (double x : cc) C += x;
         std::vector<uint64_t> bnd(m + 1, E1);
         bnd[0] = E0;
-        uint64_t s = s_lo;
-        for (uint64_t q = 1; q < m; ++q) {
-            const double want = C * (double)q / (double)m;
-            while (s < s_hi && (double)(seg_start[s + 1] - E0) + kSegCost * (double)(s - s_lo + 1) < want) ++s;
-            uint64_t e = E1;
-            if (s < s_hi) {
-                const double at = want - (double)(seg_start[s] - E0) - kSegCost * (double)(s - s_lo + 1);
-                e = seg_start[s] + (uint64_t)std::max(0.0, std::floor(at));
-                e = std::min(e, seg_start[s + 1]);
+        {
+            size_t k = 0;
+            double pre = 0;
+            for (uint64_t q = 1; q < m; ++q) {
+                const double want = C * (double)q / (double)m;
+                while (k < cc.size() && pre + 0.5 * cc[k] < want) pre += cc[k++];
+                bnd[q] = std::max(bnd[q - 1], std::min(E1, E0 + 64 * (uint64_t)k));
             }
-            bnd[q] = std::max(bnd[q - 1], std::min(e, E1));
         }
         // rounds of each task
         uint64_t sp = s_lo;  // segment containing the current entry
         for (uint64_t q = 0; q < m; ++q) {
             const uint64_t lo = bnd[q], hi = bnd[q + 1];
             SpTask t{lo, 0, (uint32_t)out->rounds.size()};
-            int64_t built = -1;
-            for (uint64_t c0 = lo; c0 < hi; c0 += 64) {
-                const uint64_t c1 = std::min(c0 + 64, hi);
-                while (seg_start[sp + 1] <= c0) ++sp;
-                uint64_t a = sp;
-                uint32_t lane_lo = 0;
-                for (;;) {
-                    const uint64_t end_a = seg_start[a + 1];
-                    const bool two = end_a < c1;  // the next segment starts inside the round
-                    const uint64_t b = two ? a + 1 : a;
-                    const uint64_t end_r = std::min(c1, seg_start[b + 1]);
-                    const uint32_t lane_hi = (uint32_t)(end_r - c0);
-                    const uint32_t cut = two ? (uint32_t)(end_a - c0) : 64u;
-                    uint32_t meta = lane_lo | lane_hi << 8 | cut << 16;
-                    if ((int64_t)a > built) {
-                        meta |= kMetaBuild0;
-                        built = (int64_t)a;
-                    }
-                    if (two && (int64_t)b > built) {
-                        meta |= kMetaBuild1;
-                        built = (int64_t)b;
-                    }
-                    if (a & 1) meta |= kMetaSlot0;  // slot of a segment = parity of its index
-                    out->rounds.push_back(SpRound{(uint32_t)(c0 - lo), seg_word[a], seg_word[b], meta});
-                    ++t.n_rounds;
-                    if (end_r >= c1) break;
-                    a = b + 1;  // starts at end_r
-                    lane_lo = lane_hi;
-                }
-            }
+            uint32_t tword = 0;  // word of the last table copied
+            walk_rounds(seg_start, lo, hi, sp,
+                        [&](uint64_t c0, uint32_t lane_lo, uint32_t lane_hi, uint32_t cut, uint64_t a, int build) {
+                            uint32_t meta = lane_lo | lane_hi << 8 | cut << 16;
+                            if (build >= 0) {
+                                meta |= build == 0 ? kMetaBuild0 : kMetaBuild1;
+                                tword = seg_word[a + build];
+                            }
+                            if (a & 1) meta |= kMetaSlot0;  // slot of a segment = parity of its index
+                            out->rounds.push_back(SpRound{(uint32_t)(c0 - lo), tword, 0, meta});
+                            ++t.n_rounds;
+                        });
             out->tasks.push_back(t);
         }
     }
@@ -637,7 +714,7 @@ lbl_status build_sparse(lbl_abs *a)
     const uint32_t n_cu = (uint32_t)device_cu_count();
     sp->tilings.resize(1 + kBatchTilings);
     for (int i = 0; i <= kBatchTilings; ++i) {
-        std::vector<uint32_t> k = i == 0 ? tiles_per_block(seg_start, rb_seg, n_cu)
+        std::vector<uint32_t> k = i == 0 ? tiles_per_block(block_costs(seg_start, rb_seg), n_cu)
                                          : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
         TilingHost h;
         make_tiling(seg_start, seg_word, rb_seg, k, &h);
@@ -651,7 +728,7 @@ lbl_status build_sparse(lbl_abs *a)
 
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)
 {
-    return up256((size_t)a->n_words * 64 * n_lane_groups * sizeof(uint64_t)) +
+    return up256((size_t)a->n_words * 256 * n_lane_groups * sizeof(uint64_t)) +
            (size_t)n_lane_groups * a->sp->tilings[t].n_tiles * kRowBlock * sizeof(uint64_t);
 }
 
@@ -660,16 +737,16 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     LBL_REQUIRE(a->sp != nullptr, "the abstraction has no sparse layout");
     const SparseLayout &sp = *a->sp;
     const SpTiling &tl = sp.tilings[0];
-    uint64_t *Oc = static_cast<uint64_t *>(ws);
-    uint64_t *P = Oc + up256((size_t)a->n_words * 64 * sizeof(uint64_t)) / sizeof(uint64_t);
+    uint64_t *Tg = static_cast<uint64_t *>(ws);
+    uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
     void *spn = span_begin(s);
-    hipLaunchKernelGGL(k_pack_cells, dim3((unsigned)(((uint64_t)a->n_words * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->n_words, Oc);
+    hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)a->n_words * 64 + 255) / 256)), dim3(256), 0, s, O,
+                       n_props, a->d_word_cell, a->n_words, Tg);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);
     hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.tasks,
-                       tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Oc, P);
+                       tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Tg, P);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
     spn = span_begin(s);

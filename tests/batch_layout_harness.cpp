@@ -52,7 +52,7 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     const GroupDesc *gs = reinterpret_cast<const GroupDesc *>(img.data() + (reinterpret_cast<uint8_t *>(b.d_groups) - base));
     std::vector<std::pair<const uint8_t *, const uint8_t *>> ow_ranges;
     for (size_t g = 0; g < p.groups.size(); ++g) {
-        const size_t ow = (size_t)gs[g].n_words * gs[g].G64 * 64 * sizeof(uint64_t);
+        const size_t ow = (size_t)gs[g].n_words * gs[g].G64 * (p.sparse ? 256 : 64) * sizeof(uint64_t);
         CHECK(inside(gs[g].Ow, ow));
         CHECK(reinterpret_cast<const uint8_t *>(gs[g].Ow) >= reinterpret_cast<uint8_t *>(b.d_ow));
         CHECK(inside(gs[g].lanes, (size_t)gs[g].G64 * 64 * sizeof(LaneDesc)));
@@ -219,8 +219,9 @@ static void check_tiling(const std::vector<uint64_t> &start, const std::vector<u
                     const uint32_t lane_lo = r.meta & 0xFF, lane_hi = (r.meta >> 8) & 0xFF, cut = (r.meta >> 16) & 0xFF;
                     CHECK(lane_lo < lane_hi && lane_hi <= 64 && cut <= 64 && (r.meta >> 27) == 0);
                     const uint32_t s0 = (r.meta & kMetaSlot0) ? 1 : 0;
-                    if (r.meta & kMetaBuild0) slot_word[s0] = r.word0;
-                    if (r.meta & kMetaBuild1) slot_word[s0 ^ 1] = r.word1;
+                    CHECK(!((r.meta & kMetaBuild0) && (r.meta & kMetaBuild1)));  // one table per round
+                    if (r.meta & kMetaBuild0) slot_word[s0] = r.tword;
+                    if (r.meta & kMetaBuild1) slot_word[s0 ^ 1] = r.tword;
                     for (uint32_t l = lane_lo; l < lane_hi; ++l) {
                         const uint64_t e = tk.lo + r.e_off + l;
                         CHECK(e < E1);
@@ -252,7 +253,7 @@ static void check_tilings()
             const uint32_t n_rb = 1 + rng() % 5, W = 16 + rng() % 300;
             random_segments(rng, n_rb, W, mode, &start, &word, &rb_seg);
             for (uint32_t target : {1u, 3u, 7u, 40u}) {
-                const std::vector<uint32_t> k = tiles_per_block(start, rb_seg, target);
+                const std::vector<uint32_t> k = tiles_per_block(block_costs(start, rb_seg), target);
                 uint64_t sum = 0;
                 for (uint32_t x : k) {
                     CHECK(x >= 1);
@@ -268,12 +269,41 @@ static void check_tilings()
     random_segments(rng, 1, 4096, 0, &start, &word, &rb_seg);
     TilingHost h;
     make_tiling(start, word, rb_seg, std::vector<uint32_t>(1, 16), &h);
-    uint32_t mx = 0, mn = ~0u;
-    for (const SpTask &t : h.tasks) {
-        mx = std::max(mx, t.n_rounds);
-        mn = std::min(mn, t.n_rounds);
+    auto per_share = [&](size_t i) { return (double)h.tasks[i].n_rounds; };
+    double mx = 0, mn = 1e30;
+    for (size_t i = 0; i < h.tasks.size(); ++i) {
+        mx = std::max(mx, per_share(i));
+        mn = std::min(mn, per_share(i));
     }
-    CHECK(mx <= mn + mn / 5 + 4);
+    CHECK(mx <= mn * 1.2 + 4);
+    // balance across blocks: a full block of large segments and a short last
+    // block of small ones (small segments cost more rounds per entry)
+    start.clear();
+    word.clear();
+    rb_seg.assign(3, 0);
+    uint64_t e = 0;
+    for (uint32_t rb = 0; rb < 2; ++rb) {
+        rb_seg[rb] = word.size();
+        for (uint32_t w = 0; w < 4096; ++w) {
+            start.push_back(e);
+            word.push_back(w);
+            e += rb == 0 ? 60 + rng() % 80 : 5 + rng() % 50;
+        }
+    }
+    rb_seg[2] = word.size();
+    start.push_back(e);
+    const std::vector<uint32_t> k = tiles_per_block(block_costs(start, rb_seg), 48);
+    CHECK(k[0] + k[1] == 48 && k[1] >= 1);
+    make_tiling(start, word, rb_seg, k, &h);
+    double sum = 0;
+    mx = 0;
+    for (size_t i = 0; i < h.tasks.size(); ++i) {
+        mx = std::max(mx, per_share(i));
+        sum += per_share(i);
+    }
+    const double mean = sum / h.tasks.size();
+    CHECK(mx <= 1.15 * mean + 3);
+    check_tiling(start, word, rb_seg, k);
 }
 
 int main()

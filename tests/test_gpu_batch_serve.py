@@ -215,15 +215,25 @@ def test_serve_result_same_alone_and_in_the_mix(abstractions):
 
 def test_serve_admission_by_memory(abstractions):
     x = big = abstractions[[k for k, y in enumerate(abstractions) if y.a.grid.n == 512][0]]
-    # a budget that holds only a few 64-column lane groups per batch still serves everything
-    need = x.a.grid.n_cells * 8  # packed masks of one 64-column frame: words x 64 lanes x 8 bytes
-    s = lbl.serve_start(hbm_budget_bytes=max(1 << 20, 3 * need), max_batch_frames=16, n_streams=1)
+    # the device bytes one 64-column request takes, as the server accounts them
+    s = lbl.serve_start(hbm_budget_bytes=1 << 30, max_batch_frames=1, n_streams=1)
+    try:
+        Od64 = torch.from_numpy(frames_for(x, 0, 0, n_props=64)).cuda()
+        Ld64 = torch.empty((x.a.n_traj, 64), dtype=torch.uint8, device="cuda")
+        assert lbl.serve_wait(s, lbl.serve_submit(s, x.h, Od64, 64, Ld64)) == lbl.OK
+        need = lbl.serve_stats(s)["budget_high_water"]
+    finally:
+        lbl.serve_stop(s)
+    assert need > 0
+    say(f"one 64-column request on {x.a.n_traj} x {x.a.grid.n}^2 takes {need} bytes")
+    # a budget that holds only a few such requests per batch still serves everything
+    s = lbl.serve_start(hbm_budget_bytes=3 * need, max_batch_frames=16, n_streams=1)
     try:
         reqs = requests([x] * 1, 12, seed=4)
         serve_and_check(s, reqs, n_threads=2)
         st = lbl.serve_stats(s)
         assert st["batches"] >= 2, st
-        assert st["budget_high_water"] <= max(1 << 20, 3 * need)
+        assert st["budget_high_water"] <= 3 * need
     finally:
         lbl.serve_stop(s)
     # a request larger than a slot's share is rejected with ENOMEM
