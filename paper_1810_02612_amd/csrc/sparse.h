@@ -54,8 +54,13 @@ struct SpTiling {
     SpTask *tasks = nullptr;     // device [n_tiles * kTileWaves]
     SpRound *rounds = nullptr;   // device [n_rounds]
     uint32_t *rb_tile = nullptr; // device [n_rb + 1]
+    uint32_t *block_tile = nullptr; // device [n_tiles] launch order of a one-frame launch
     std::vector<uint32_t> rb_tile_host;
 };
+
+// XCDs of an MI355X.  Workgroup b of a launch runs on XCD b % kXcds, and
+// each XCD has its own L2.
+constexpr uint32_t kXcds = 8;
 
 // Device-resident sparse layout of one abstraction.
 struct SparseLayout {
@@ -89,10 +94,15 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
 // rb_seg[rb + 1] the segments of row block rb.  tiles_rb[rb] >= 1 tiles per
 // row block; the block's tasks start at 64-entry chunk boundaries and have
 // equal cost (rounds, plus a charge per table copy) as the block is walked.
+// block_tile: the tile workgroup b of a one-frame launch runs; tiles are
+// ranked by the word at their middle entry and the ranks split into kXcds
+// consecutive groups, one per XCD, so that each XCD's L2 holds the nibble
+// tables of about 1 / kXcds of the words.
 struct TilingHost {
     std::vector<SpTask> tasks;
     std::vector<SpRound> rounds;
     std::vector<uint32_t> rb_tile;
+    std::vector<uint32_t> block_tile;
 };
 void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
                  const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out);

@@ -330,16 +330,18 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
         reinterpret_cast<ulonglong2 *>(Pt)[i] = reinterpret_cast<const ulonglong2 *>(acc)[i];
 }
 
-// One workgroup per tile of a single frame.  Partials P[tile][kRowBlock].
+// One workgroup per tile of a single frame, workgroup b running tile
+// block_tile[b].  Partials P[tile][kRowBlock].
 template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
-k_label_tiles(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
+k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks,
+              const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
               const uint64_t *__restrict__ sp_val, uint64_t max_entry, const uint64_t *__restrict__ Tg,
               uint64_t *__restrict__ P)
 {
     extern __shared__ uint64_t lds[];
-    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Tg, 256, blockIdx.x, P + (uint64_t)blockIdx.x * kRowBlock,
-                     lds);
+    const uint32_t tile = block_tile[blockIdx.x];
+    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Tg, 256, tile, P + (uint64_t)tile * kRowBlock, lds);
 }
 
 // One workgroup per (pass, tile, lane group) of a batch.  The pass's nibble
@@ -587,6 +589,31 @@ void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint3
             out->tasks.push_back(t);
         }
     }
+    // launch order: tiles ranked by the word at their middle entry, the ranks
+    // split into kXcds consecutive groups, group g taking blocks g, g + kXcds, ...
+    const uint32_t n_tiles = (uint32_t)(out->tasks.size() / kTileWaves);
+    std::vector<std::pair<uint32_t, uint32_t>> key(n_tiles);
+    for (uint32_t i = 0; i < n_tiles; ++i) {
+        const SpTask &f = out->tasks[(size_t)i * kTileWaves];
+        const SpTask &l = out->tasks[(size_t)i * kTileWaves + kTileWaves - 1];
+        uint64_t hi = l.lo;  // end of the tile's entries: its last task's end
+        for (uint32_t r = 0; r < l.n_rounds; ++r) {
+            const SpRound &x = out->rounds[l.round0 + r];
+            hi = std::max<uint64_t>(hi, l.lo + x.e_off + ((x.meta >> 8) & 0xFFu));
+        }
+        const uint64_t mid = (f.lo + hi) / 2;
+        uint32_t w = 0;
+        if (hi > f.lo) {
+            const uint64_t sidx = std::upper_bound(seg_start.begin(), seg_start.end(), mid) - seg_start.begin() - 1;
+            w = seg_word[std::min<uint64_t>(sidx, seg_word.size() - 1)];
+        }
+        key[i] = {w, i};
+    }
+    std::stable_sort(key.begin(), key.end());
+    out->block_tile.assign(n_tiles, 0);
+    uint32_t rank = 0;
+    for (uint32_t g = 0; g < kXcds; ++g)
+        for (uint32_t b = g; b < n_tiles; b += kXcds) out->block_tile[b] = key[rank++].second;
 }
 
 SparseLayout::~SparseLayout()
@@ -597,6 +624,7 @@ SparseLayout::~SparseLayout()
         (void)hipFree(t.tasks);
         (void)hipFree(t.rounds);
         (void)hipFree(t.rb_tile);
+        (void)hipFree(t.block_tile);
     }
 }
 
@@ -629,7 +657,11 @@ static lbl_status upload_tiling(const TilingHost &h, SpTiling *t, size_t *bytes)
         LBL_HIP_TRY(hipMemcpy(t->rounds, h.rounds.data(), h.rounds.size() * sizeof(SpRound), hipMemcpyHostToDevice));
     LBL_HIP_TRY(hipMalloc(&t->rb_tile, h.rb_tile.size() * sizeof(uint32_t)));
     LBL_HIP_TRY(hipMemcpy(t->rb_tile, h.rb_tile.data(), h.rb_tile.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    *bytes += h.tasks.size() * sizeof(SpTask) + h.rounds.size() * sizeof(SpRound) + h.rb_tile.size() * sizeof(uint32_t);
+    LBL_HIP_TRY(hipMalloc(&t->block_tile, std::max<size_t>(h.block_tile.size(), 1) * sizeof(uint32_t)));
+    LBL_HIP_TRY(hipMemcpy(t->block_tile, h.block_tile.data(), h.block_tile.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+    *bytes += h.tasks.size() * sizeof(SpTask) + h.rounds.size() * sizeof(SpRound) +
+              (h.rb_tile.size() + h.block_tile.size()) * sizeof(uint32_t);
     return LBL_OK;
 }
 
@@ -745,8 +777,8 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);
-    hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.tasks,
-                       tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Tg, P);
+    hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.block_tile,
+                       tl.tasks, tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Tg, P);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
     spn = span_begin(s);

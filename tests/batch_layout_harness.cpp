@@ -200,6 +200,11 @@ static void check_tiling(const std::vector<uint64_t> &start, const std::vector<u
     for (uint32_t x : k) n_tiles += x;
     CHECK(h.tasks.size() == n_tiles * kTileWaves);
     CHECK(h.rb_tile.size() == n_rb + 1 && h.rb_tile[0] == 0 && h.rb_tile[n_rb] == n_tiles);
+    // the launch order is a permutation of the tiles
+    std::vector<uint32_t> order = h.block_tile;
+    std::sort(order.begin(), order.end());
+    CHECK(order.size() == n_tiles);
+    for (uint32_t i = 0; i < order.size(); ++i) CHECK(order[i] == i);
     const uint64_t nnz = start.back();
     std::vector<uint8_t> seen(nnz, 0);
     for (size_t rb = 0; rb < n_rb; ++rb) {
