@@ -156,14 +156,20 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
 }
 
 // One wavefront per word, one lane per cell: the mask of the propositions
-// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].
+// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  The
+// word's first cell is read once per wavefront (a scalar load); lane b's
+// cell lies dy rows and dx columns from it, x taking the odd bits of b.
 __global__ void __launch_bounds__(256)
-k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell,
+k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
               uint32_t n_words, uint64_t *__restrict__ Tg)
 {
-    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // w * 64 + b
-    if (idx >= (uint64_t)n_words * 64) return;  // whole wavefronts (n_words * 64 is a multiple of 64)
-    const uint8_t *src = O + (uint64_t)word_cell[idx] * n_props;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= n_words) return;  // whole wavefronts
+    const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
+    const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
+    const uint64_t cell = (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
+    const uint8_t *src = O + cell * n_props;
     uint64_t m = 0;
     if ((n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(O) & 15u) == 0) {
         for (uint32_t p = 0; p < n_props; p += 16) {
@@ -174,7 +180,7 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
     } else {
         for (uint32_t p = 0; p < n_props; ++p) m |= (uint64_t)(src[p] != 0) << p;
     }
-    write_tables(m, Tg + (idx >> 6) * 256, threadIdx.x & 63);
+    write_tables(m, Tg + (uint64_t)w * 256, lane);
 }
 
 
@@ -400,26 +406,50 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
 
 __device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204081u) & 0x01010101u; }
 
-// One thread per row: OR of the row's partials (coalesced over rows), then
-// the row's n_props label bytes.  16-byte stores when a row is whole 16-byte
-// units, else 4-byte, else single bytes.
+// Rows' label bytes from their partials.  When n_props is a multiple of 16
+// (and L 16-byte aligned) one wavefront takes 64 consecutive rows: lane j ORs
+// the partials of row t0 + j (coalesced over rows), then the rows' bytes are
+// written as consecutive 16-byte units, lane l writing units l, l + 64, ...
+// of the block's n_props * 64 bytes, fetching the bits of each unit's row
+// from the lane that holds them.  Otherwise one thread per row, 4-byte or
+// single-byte stores.
 __global__ void __launch_bounds__(256)
 k_combine(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile, uint64_t n_traj, uint32_t n_props,
           uint8_t *__restrict__ L)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const bool v16 = (n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(L) & 15u) == 0;
+    if (v16) {
+        const uint32_t lane = threadIdx.x & 63;
+        const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+        const uint64_t n_groups = (n_traj + 63) / 64;
+        const uint32_t upr = n_props / 16;  // 16-byte units per row: 1 .. 4
+        const uint32_t shift = upr == 1 ? 0 : upr == 2 ? 1 : upr == 4 ? 2 : 32;  // 32: not a power of two
+        for (uint64_t grp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; grp < n_groups; grp += n_waves) {
+            const uint64_t t0 = grp * 64, t = t0 + lane;
+            const uint64_t bits = t < n_traj ? row_partials(P, rb_tile, t) : 0ull;
+            const uint32_t units = (uint32_t)min<uint64_t>(64, n_traj - t0) * upr;
+            uint4 *dst = reinterpret_cast<uint4 *>(L + t0 * n_props);
+            // uniform trip count: every lane takes part in the shuffles
+            for (uint32_t ub = 0; ub < units; ub += 64) {
+                const uint32_t u = ub + lane;  // < 64 * upr, so row < 64
+                const uint32_t row = min(shift < 32 ? u >> shift : u / upr, 63u);
+                const uint32_t c = u - row * upr;
+                const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)bits, (int)row);
+                const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(bits >> 32), (int)row);
+                const uint32_t b = (uint32_t)((((uint64_t)hi << 32) | lo) >> (16 * c)) & 0xFFFFu;
+                if (u < units)
+                    dst[u] = make_uint4(spread_nib(b & 0xFu), spread_nib((b >> 4) & 0xFu), spread_nib((b >> 8) & 0xFu),
+                                        spread_nib(b >> 12));
+            }
+        }
+        return;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const bool v4 = (n_props & 3u) == 0 && (reinterpret_cast<uintptr_t>(L) & 3u) == 0;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_traj; t += stride) {
         const uint64_t bits = row_partials(P, rb_tile, t);
         uint8_t *dst = L + t * n_props;
-        if (v16) {
-            for (uint32_t p = 0; p < n_props; p += 16) {
-                const uint32_t b = (uint32_t)(bits >> p) & 0xFFFFu;
-                *reinterpret_cast<uint4 *>(dst + p) = make_uint4(spread_nib(b & 0xFu), spread_nib((b >> 4) & 0xFu),
-                                                                 spread_nib((b >> 8) & 0xFu), spread_nib(b >> 12));
-            }
-        } else if (v4) {
+        if (v4) {
             for (uint32_t p = 0; p < n_props; p += 4)
                 *reinterpret_cast<uint32_t *>(dst + p) = spread_nib((uint32_t)(bits >> p) & 0xFu);
         } else {
@@ -773,7 +803,7 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
     void *spn = span_begin(s);
     hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)a->n_words * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->n_words, Tg);
+                       n_props, a->d_word_cell, a->nx, a->n_words, Tg);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);

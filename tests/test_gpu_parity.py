@@ -180,6 +180,9 @@ def test_cfg3_full_size_sampled_rows():
 @pytest.mark.parametrize("nx,ny,n_traj,n_props", [
     (8, 8, 1, 1), (8, 8, 3, 64), (24, 8, 65, 7), (24, 40, 130, 17), (64, 64, 1007, 33),
     (40, 24, 257, 63), (136, 8, 33, 16), (8, 136, 77, 2),
+    # 48 and 32 columns (three and two 16-byte units per row), 8257 rows: two
+    # row blocks of the sparse layout, the second one 65 rows long
+    (16, 16, 8257, 48), (32, 16, 130, 32),
 ])
 def test_ragged_shapes(nx, ny, n_traj, n_props):
     rng = np.random.default_rng(nx * 1000 + ny + n_traj)
