@@ -261,20 +261,28 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
             uint32_t r;        // its local row
             ulonglong2 tb[2];  // this lane's 32 bytes of the table the round builds
         };
-        // Round records are read with scalar loads one round ahead of use.
-        // Every vector load is unconditional at a clamped, in-bounds address
-        // (branches around loads would make the compiler wait for all of
-        // them); validity is applied when the round is processed.
-        SpRound rec_next = rr[0];
+        // Round records are read with vector loads (lane l, l < 4, holding
+        // word l of the record) one round before the round's own loads are
+        // issued, two rounds before it is processed: a scalar load here would
+        // make every LDS wait of the round also wait for it.  Every vector
+        // load is unconditional at a clamped, in-bounds address (branches
+        // around loads would make the compiler wait for all of them);
+        // validity is applied when the round is processed.
+        auto load_rec = [&](uint32_t i) {
+            return reinterpret_cast<const uint32_t *>(rr + min(i, n - 1))[lane & 3u];
+        };
+        uint32_t rec_next = load_rec(0);
         auto fetch = [&](Stage &st, uint32_t i) {
-            const SpRound rec = rec_next;
-            rec_next = rr[min(i + 1, n - 1)];
-            st.e_off = rec.e_off;
-            st.meta = rec.meta;
-            const uint64_t e = min(tk.lo + rec.e_off + lane, max_entry);
+            const uint32_t rv = rec_next;
+            rec_next = load_rec(i + 1);
+            const uint32_t e_off = (uint32_t)__builtin_amdgcn_readlane((int)rv, 0);
+            const uint32_t tword = (uint32_t)__builtin_amdgcn_readlane((int)rv, 1);
+            st.e_off = e_off;
+            st.meta = (uint32_t)__builtin_amdgcn_readlane((int)rv, 3);
+            const uint64_t e = min(tk.lo + e_off + lane, max_entry);
             st.x = sp_val[e];
             st.r = sp_row[e];
-            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)rec.tword * tg_stride) + 2 * lane;
+            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)tword * tg_stride) + 2 * lane;
             st.tb[0] = src[0];
             st.tb[1] = src[1];
         };
