@@ -147,13 +147,6 @@ k_seg_fill(const uint64_t *__restrict__ wm_ptr, const uint32_t *__restrict__ wm_
 
 // ---------------------------------------------------------------- per frame
 
-// Nonzero bytes of a 32-bit word -> 4 bits (bit k for byte k).
-__device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
-{
-    const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // high bit of each byte: byte != 0
-    const uint32_t h = y & 0x80808080u;
-    return ((h >> 7) | (h >> 14) | (h >> 21) | (h >> 28)) & 0xFu;
-}
 
 // One wavefront per word, one lane per cell: the mask of the propositions
 // cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  The
@@ -169,18 +162,7 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
     const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
     const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
     const uint64_t cell = (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
-    const uint8_t *src = O + cell * n_props;
-    uint64_t m = 0;
-    if ((n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(O) & 15u) == 0) {
-        for (uint32_t p = 0; p < n_props; p += 16) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(src + p);
-            const uint64_t bits = nz_bytes(q.x) | (nz_bytes(q.y) << 4) | (nz_bytes(q.z) << 8) | (nz_bytes(q.w) << 12);
-            m |= bits << p;
-        }
-    } else {
-        for (uint32_t p = 0; p < n_props; ++p) m |= (uint64_t)(src[p] != 0) << p;
-    }
-    write_tables(m, Tg + (uint64_t)w * 256, lane);
+    write_tables(byte_mask(O + cell * n_props, n_props), Tg + (uint64_t)w * 256, lane);
 }
 
 
@@ -411,8 +393,6 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
         }
     }
 }
-
-__device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204081u) & 0x01010101u; }
 
 // Rows' label bytes from their partials.  When n_props is a multiple of 16
 // (and L 16-byte aligned) one wavefront takes 64 consecutive rows: lane j ORs

@@ -7,6 +7,37 @@
 
 namespace lbl {
 
+// Nonzero bytes of a 32-bit word -> 4 bits (bit k for byte k).
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
+{
+    const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // high bit of each byte: byte != 0
+    const uint32_t h = y & 0x80808080u;
+    return ((h >> 7) | (h >> 14) | (h >> 21) | (h >> 28)) & 0xFu;
+}
+
+// Four bits -> four bytes 0/1 (bit k to byte k).
+__device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204081u) & 0x01010101u; }
+
+// Bit p set iff byte p of src[0 .. n) is non-zero, n <= 64; 16- or 4-byte
+// loads when n and the address allow.
+__device__ __forceinline__ uint64_t byte_mask(const uint8_t *src, uint32_t n)
+{
+    uint64_t m = 0;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src);
+    if ((n & 15u) == 0 && (a & 15u) == 0) {
+        for (uint32_t p = 0; p < n; p += 16) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(src + p);
+            const uint64_t bits = nz_bytes(q.x) | (nz_bytes(q.y) << 4) | (nz_bytes(q.z) << 8) | (nz_bytes(q.w) << 12);
+            m |= bits << p;
+        }
+    } else if ((n & 3u) == 0 && (a & 3u) == 0) {
+        for (uint32_t p = 0; p < n; p += 4) m |= (uint64_t)nz_bytes(*reinterpret_cast<const uint32_t *>(src + p)) << p;
+    } else {
+        for (uint32_t p = 0; p < n; ++p) m |= (uint64_t)(src[p] != 0) << p;
+    }
+    return m;
+}
+
 // Value of lane C of each group of four lanes (DPP quad permutation).
 template <int C>
 __device__ __forceinline__ uint64_t quad_bcast(uint64_t v)
