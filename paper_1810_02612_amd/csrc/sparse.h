@@ -13,6 +13,12 @@ namespace lbl {
 constexpr uint32_t kRowBlock = 8192;
 // Wavefronts per tile workgroup (one workgroup per CU: 16 wavefronts).
 constexpr uint32_t kTileWaves = 16;
+// Zeroed entries stored past the last entry of the layout, so that every lane
+// of a round may load its entry without a bounds check.
+constexpr uint64_t kEntryPad = 64;
+// Rounds a wavefront has in flight (records, entries and table data loaded
+// ahead of the round being processed).
+constexpr int kStages = 3;
 // Nibble tables a wavefront holds at once (a round touches at most two
 // segments).
 constexpr uint32_t kRing = 2;

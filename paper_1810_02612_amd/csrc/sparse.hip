@@ -187,6 +187,15 @@ __device__ __forceinline__ uint32_t add_byte(uint32_t base, uint32_t bytes)
     return r;
 }
 
+// Lane l gets b where bit l of mask (wavefront-uniform) is set, else a: one
+// v_cndmask with the mask read from a scalar register pair.
+__device__ __forceinline__ uint32_t select_by_lane(uint64_t mask, uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+    return r;
+}
+
 typedef __attribute__((address_space(3))) const uint64_t lds_u64;
 
 // Entry of table row q at LDS byte address addr + q * kTabRow * 8.
@@ -220,7 +229,7 @@ __device__ __forceinline__ void copy_tables(const ulonglong2 (&v)[2], uint64_t *
 template <int WAVES>
 __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds,
                                           const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
-                                          uint64_t max_entry, const uint64_t *__restrict__ Tg, uint64_t tg_stride,
+                                          const uint64_t *__restrict__ Tg, uint64_t tg_stride,
                                           uint64_t tile, uint64_t *__restrict__ Pt, uint64_t *lds)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -238,37 +247,47 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
         const SpRound *rr = rounds + tk.round0;
 
         struct Stage {
-            uint32_t e_off, meta;
+            uint32_t rec;      // lanes 0-3: the record of the stage's next round
+            uint32_t meta;
             uint64_t x;        // this lane's word value
-            uint32_t r;        // its local row
+            uint16_t r;        // its local row
             ulonglong2 tb[2];  // this lane's 32 bytes of the table the round builds
         };
-        // Round records are read with vector loads (lane l, l < 4, holding
-        // word l of the record) one round before the round's own loads are
-        // issued, two rounds before it is processed: a scalar load here would
-        // make every LDS wait of the round also wait for it.  Every vector
-        // load is unconditional at a clamped, in-bounds address (branches
-        // around loads would make the compiler wait for all of them);
-        // validity is applied when the round is processed.
+        // kStages rounds are in flight: round i is fetched (its entries and
+        // table data loaded) kStages - 1 rounds before it is processed, and
+        // its record (lane l, l < 4, holding word l) kStages rounds before
+        // that fetch, so neither wait is on the round's critical path.  A
+        // scalar load of the record would instead make every LDS wait also
+        // wait for it (the two share one counter).  Every vector load is
+        // unconditional and in bounds (the entry arrays carry 64 entries of
+        // padding past the last one, and the record index is clamped), since
+        // branches around loads would make the compiler wait for all of them;
+        // validity is applied when the round is processed.  Each load takes a
+        // wavefront-uniform base and a per-lane offset, so that no per-lane
+        // 64-bit address arithmetic is needed.
         auto load_rec = [&](uint32_t i) {
             return reinterpret_cast<const uint32_t *>(rr + min(i, n - 1))[lane & 3u];
         };
-        uint32_t rec_next = load_rec(0);
+        const uint64_t *val_t = sp_val + tk.lo;
+        const uint16_t *row_t = sp_row + tk.lo;
         auto fetch = [&](Stage &st, uint32_t i) {
-            const uint32_t rv = rec_next;
-            rec_next = load_rec(i + 1);
-            const uint32_t e_off = (uint32_t)__builtin_amdgcn_readlane((int)rv, 0);
-            const uint32_t tword = (uint32_t)__builtin_amdgcn_readlane((int)rv, 1);
-            st.e_off = e_off;
-            st.meta = (uint32_t)__builtin_amdgcn_readlane((int)rv, 3);
-            const uint64_t e = min(tk.lo + e_off + lane, max_entry);
-            st.x = sp_val[e];
-            st.r = sp_row[e];
-            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)tword * tg_stride) + 2 * lane;
-            st.tb[0] = src[0];
-            st.tb[1] = src[1];
+            // the fields are read before the register is reloaded, so that the
+            // reload can take the same register (no copy waiting for it)
+            const uint32_t e_off = (uint32_t)__builtin_amdgcn_readlane((int)st.rec, 0);
+            const uint32_t tword = (uint32_t)__builtin_amdgcn_readlane((int)st.rec, 1);
+            st.meta = (uint32_t)__builtin_amdgcn_readlane((int)st.rec, 3);
+            st.rec = load_rec(i + kStages);
+            st.x = (val_t + e_off)[lane];
+            st.r = (row_t + e_off)[lane];
+            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)tword * tg_stride);
+            st.tb[0] = src[2 * lane];
+            st.tb[1] = src[2 * lane + 1];
         };
 
+        // the two slot addresses live in vector registers for the whole walk
+        uint32_t slot_a, slot_b;
+        asm("v_mov_b32 %0, %1" : "=v"(slot_a) : "s"(lds_addr(tab)));
+        asm("v_mov_b32 %0, %1" : "=v"(slot_b) : "s"(lds_addr(tab) + kTabWords * 8));
         auto process = [&](const Stage &st) {
             const uint32_t meta = st.meta;
             const uint32_t s0 = (meta & kMetaSlot0) ? 1u : 0u;
@@ -279,22 +298,41 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
             // compiler from moving LDS accesses across this point.
             __builtin_amdgcn_wave_barrier();
             const uint32_t lane_lo = meta & 0xFFu, lane_hi = (meta >> 8) & 0xFFu, cut = (meta >> 16) & 0xFFu;
-            if (lane >= lane_lo && lane < lane_hi) {
-                const uint64_t *t = tab + (s0 ^ (lane >= cut ? 1u : 0u)) * kTabWords;
-                // byte k of ev[h] (od[h]) is 8 x nibble 2k (2k + 1) of half h of
-                // the word value: the byte offset of its entry in the table row
-                const uint32_t lo = (uint32_t)st.x, hi = (uint32_t)(st.x >> 32);
-                const uint32_t ev[2] = {(lo << 3) & 0x78787878u, (hi << 3) & 0x78787878u};
-                const uint32_t od[2] = {(lo >> 1) & 0x78787878u, (hi >> 1) & 0x78787878u};
-                const uint32_t tb = lds_addr(t);
-                uint64_t a = 0;
+            // lanes below cut read slot s0, the others slot s0 ^ 1: the lane
+            // mask of slot-b readers is formed in scalar registers
+            const uint64_t upper = cut >= 64 ? 0ull : (~0ull << cut);
+            const uint32_t tb = select_by_lane(s0 ? ~upper : upper, slot_a, slot_b);
+            {
+                // every lane looks up its word value (an address inside the
+                // slot whatever the value); lanes outside [lane_lo, lane_hi)
+                // then drop their result, which costs less than a branch.
+                // Byte k of ev (od) is 8 x nibble 2k (2k + 1) of the word
+                // value: the byte offset of its entry in the table row
+                const uint64_t m = 0x7878787878787878ull;
+                const uint64_t ev = (st.x << 3) & m, od = (st.x >> 1) & m;
+                const uint32_t e[2] = {(uint32_t)ev, (uint32_t)(ev >> 32)};
+                const uint32_t o[2] = {(uint32_t)od, (uint32_t)(od >> 32)};
+                // all sixteen reads are issued before the first result is used
+                uint64_t q[16];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    a |= lds_entry(add_byte<0>(tb, ev[h]), 8 * h + 0) | lds_entry(add_byte<0>(tb, od[h]), 8 * h + 1);
-                    a |= lds_entry(add_byte<1>(tb, ev[h]), 8 * h + 2) | lds_entry(add_byte<1>(tb, od[h]), 8 * h + 3);
-                    a |= lds_entry(add_byte<2>(tb, ev[h]), 8 * h + 4) | lds_entry(add_byte<2>(tb, od[h]), 8 * h + 5);
-                    a |= lds_entry(add_byte<3>(tb, ev[h]), 8 * h + 6) | lds_entry(add_byte<3>(tb, od[h]), 8 * h + 7);
+                    q[8 * h + 0] = lds_entry(add_byte<0>(tb, e[h]), 8 * h + 0);
+                    q[8 * h + 1] = lds_entry(add_byte<0>(tb, o[h]), 8 * h + 1);
+                    q[8 * h + 2] = lds_entry(add_byte<1>(tb, e[h]), 8 * h + 2);
+                    q[8 * h + 3] = lds_entry(add_byte<1>(tb, o[h]), 8 * h + 3);
+                    q[8 * h + 4] = lds_entry(add_byte<2>(tb, e[h]), 8 * h + 4);
+                    q[8 * h + 5] = lds_entry(add_byte<2>(tb, o[h]), 8 * h + 5);
+                    q[8 * h + 6] = lds_entry(add_byte<3>(tb, e[h]), 8 * h + 6);
+                    q[8 * h + 7] = lds_entry(add_byte<3>(tb, o[h]), 8 * h + 7);
                 }
+                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);  // the sixteen LDS reads first
+                uint64_t a = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) a |= q[k];
+                const uint64_t below_hi = lane_hi >= 64 ? ~0ull : ((1ull << lane_hi) - 1ull);
+                const uint64_t act = below_hi & (~0ull << lane_lo);
+                a = ((uint64_t)select_by_lane(act, 0u, (uint32_t)(a >> 32)) << 32) | select_by_lane(act, 0u, (uint32_t)a);
+                // zero results are skipped: an OR of zero still costs LDS time
                 if (a) __hip_atomic_fetch_or(acc + st.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             __builtin_amdgcn_wave_barrier();  // later builds overwrite these tables
@@ -304,26 +342,30 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
             asm volatile("" ::"v"(st.tb[0].x), "v"(st.tb[0].y), "v"(st.tb[1].x), "v"(st.tb[1].y));
         };
 
-        // three rounds in rotation: while one is processed the loads of the
-        // next two are in flight.  When n is not a multiple of three the last
-        // round is processed again (fetch clamps to it), which changes
+        // the stages in rotation.  When n is not a multiple of kStages the
+        // last round is processed again (fetch clamps to it), which changes
         // nothing: its tables are rebuilt with the same contents and OR is
         // idempotent.
-        Stage A, B, C;
-        fetch(A, 0);
-        fetch(B, 1);
-        for (uint32_t i = 0; i < n; i += 3) {
-            fetch(C, i + 2);
-            process(A);
-            fetch(A, i + 3);
-            process(B);
-            fetch(B, i + 4);
-            process(C);
+        Stage st[kStages];
+#pragma unroll
+        for (int k = 0; k < kStages; ++k) st[k].rec = load_rec(k);
+#pragma unroll
+        for (int k = 0; k + 1 < kStages; ++k) fetch(st[k], k);
+        for (uint32_t i = 0; i < n; i += kStages) {
+#pragma unroll
+            for (int k = 0; k < kStages; ++k) {
+                fetch(st[(k + kStages - 1) % kStages], i + k + kStages - 1);
+                process(st[k]);
+            }
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
-        reinterpret_cast<ulonglong2 *>(Pt)[i] = reinterpret_cast<const ulonglong2 *>(acc)[i];
+    // streaming stores: the partials are read once, by the combine kernel
+    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES) {
+        const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(acc)[i];
+        __builtin_nontemporal_store(v.x, Pt + 2 * i);
+        __builtin_nontemporal_store(v.y, Pt + 2 * i + 1);
+    }
 }
 
 // One workgroup per tile of a single frame, workgroup b running tile
@@ -332,12 +374,12 @@ template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks,
               const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, uint64_t max_entry, const uint64_t *__restrict__ Tg,
+              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg,
               uint64_t *__restrict__ P)
 {
     extern __shared__ uint64_t lds[];
     const uint32_t tile = block_tile[blockIdx.x];
-    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, max_entry, Tg, 256, tile, P + (uint64_t)tile * kRowBlock, lds);
+    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, Tg, 256, tile, P + (uint64_t)tile * kRowBlock, lds);
 }
 
 // One workgroup per (pass, tile, lane group) of a batch.  The pass's nibble
@@ -349,7 +391,7 @@ k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__rest
     extern __shared__ uint64_t lds[];
     const TileItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.max_entry, g.Ow + (uint64_t)it.gi * 256,
+    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.Ow + (uint64_t)it.gi * 256,
                      (uint64_t)g.G64 * 256, it.tile,
                      g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
 }
@@ -734,8 +776,12 @@ lbl_status build_sparse(lbl_abs *a)
     LBL_HIP_TRY(hipMalloc(&d_seg, (n_seg + 1) * sizeof(uint64_t)));
     std::unique_ptr<uint64_t, decltype(&hipFree)> g_seg(d_seg, &hipFree);
     LBL_HIP_TRY(hipMemcpy(d_seg, seg.data(), (n_seg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
-    LBL_HIP_TRY(hipMalloc(&sp->row, std::max<uint64_t>(nnz, 1) * sizeof(uint16_t)));
-    LBL_HIP_TRY(hipMalloc(&sp->val, std::max<uint64_t>(nnz, 1) * sizeof(uint64_t)));
+    // kEntryPad zeroed entries past the last one: a round's lanes load
+    // entries up to 63 past its range without bounds checks
+    LBL_HIP_TRY(hipMalloc(&sp->row, (nnz + kEntryPad) * sizeof(uint16_t)));
+    LBL_HIP_TRY(hipMalloc(&sp->val, (nnz + kEntryPad) * sizeof(uint64_t)));
+    LBL_HIP_TRY(hipMemset(sp->row + nnz, 0, kEntryPad * sizeof(uint16_t)));
+    LBL_HIP_TRY(hipMemset(sp->val + nnz, 0, kEntryPad * sizeof(uint64_t)));
     hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, d_val, W,
                        sp->n_rb, d_seg, sp->row, sp->val);
     LBL_HIP_TRY(hipGetLastError());
@@ -796,7 +842,7 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     span_end(spn, s, 0);
     spn = span_begin(s);
     hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.block_tile,
-                       tl.tasks, tl.rounds, sp.row, sp.val, std::max<uint64_t>(sp.nnz, 1) - 1, Tg, P);
+                       tl.tasks, tl.rounds, sp.row, sp.val, Tg, P);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
     spn = span_begin(s);
