@@ -94,6 +94,9 @@ size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t =
 // Pack O, label through the tiled layout, write L (device pointers).
 lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s);
 
+// Relative work of wavefront w of a tile workgroup (tasks are sized to it).
+double wave_share(uint32_t w);
+
 // Host-side: the tasks and rounds of one tiling of a row-block-ordered
 // segment list (exposed for host tests).  seg_start[s] .. seg_start[s + 1]
 // are the entries of segment s, seg_word[s] its word, rb_seg[rb] ..

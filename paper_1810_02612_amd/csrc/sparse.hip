@@ -501,6 +501,21 @@ size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 // Cost of a round, in rounds: one, plus this much when it copies a table in.
 constexpr double kBuildCost = 0.25;
 
+}  // namespace
+
+// Relative work of wavefront w of a tile workgroup.  Wavefronts w, w + 4,
+// w + 8 and w + 12 share a SIMD, and the SIMD issues for the oldest of them
+// first: measured at full load, their round rates fall with age in about
+// these proportions, and work sized to them lets the four finish together
+// (equal shares leave the last ones running alone at a lower SIMD throughput).
+double wave_share(uint32_t w)
+{
+    static const double share[4] = {2.6, 2.0, 1.6, 1.3};
+    return share[(w % kTileWaves) / 4];
+}
+
+namespace {
+
 
 
 // The rounds of entries [lo, hi) of one row block as one wavefront walks them
@@ -618,13 +633,18 @@ void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint3
         const std::vector<double> cc = chunk_costs(seg_start, rb_seg, rb);
         double C = 0;
         for (double x : cc) C += x;
+        // task q's share of the block's cost is proportional to
+        // wave_share(q % kTileWaves)
+        double Wsum = 0;
+        for (uint64_t q = 0; q < m; ++q) Wsum += wave_share((uint32_t)(q % kTileWaves));
         std::vector<uint64_t> bnd(m + 1, E1);
         bnd[0] = E0;
         {
             size_t k = 0;
-            double pre = 0;
+            double pre = 0, wq = 0;
             for (uint64_t q = 1; q < m; ++q) {
-                const double want = C * (double)q / (double)m;
+                wq += wave_share((uint32_t)((q - 1) % kTileWaves));
+                const double want = C * wq / Wsum;
                 while (k < cc.size() && pre + 0.5 * cc[k] < want) pre += cc[k++];
                 bnd[q] = std::max(bnd[q - 1], std::min(E1, E0 + 64 * (uint64_t)k));
             }

@@ -270,11 +270,12 @@ static void check_tilings()
             }
             check_tiling(start, word, rb_seg, std::vector<uint32_t>(n_rb, 2));
         }
-    // balance: tasks of equal cost within a block (typical sizes, one block)
+    // balance: tasks of equal cost per share within a block (typical sizes, one block)
     random_segments(rng, 1, 4096, 0, &start, &word, &rb_seg);
     TilingHost h;
     make_tiling(start, word, rb_seg, std::vector<uint32_t>(1, 16), &h);
-    auto per_share = [&](size_t i) { return (double)h.tasks[i].n_rounds; };
+    // rounds per unit of the task's wave share (tasks are sized to the shares)
+    auto per_share = [&](size_t i) { return (double)h.tasks[i].n_rounds / wave_share((uint32_t)(i % kTileWaves)); };
     double mx = 0, mn = 1e30;
     for (size_t i = 0; i < h.tasks.size(); ++i) {
         mx = std::max(mx, per_share(i));
