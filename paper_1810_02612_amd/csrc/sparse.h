@@ -61,6 +61,7 @@ struct SpTiling {
     SpRound *rounds = nullptr;   // device [n_rounds]
     uint32_t *rb_tile = nullptr; // device [n_rb + 1]
     uint32_t *block_tile = nullptr; // device [n_tiles] launch order of a one-frame launch
+    SpTask *tasks_launch = nullptr; // device [n_tiles * kTileWaves] the tasks of workgroup b at b * kTileWaves
     std::vector<uint32_t> rb_tile_host;
 };
 

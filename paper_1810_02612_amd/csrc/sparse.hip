@@ -227,10 +227,10 @@ __device__ __forceinline__ void copy_tables(const ulonglong2 (&v)[2], uint64_t *
 // Pt[0 .. kRowBlock).  Tg + w * tg_stride holds the 256 nibble-table entries
 // of word w.
 template <int WAVES>
-__device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, const SpRound *__restrict__ rounds,
+__device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, const SpRound *__restrict__ rounds,
                                           const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
                                           const uint64_t *__restrict__ Tg, uint64_t tg_stride,
-                                          uint64_t tile, uint64_t *__restrict__ Pt, uint64_t *lds)
+                                          uint64_t *__restrict__ Pt, uint64_t *lds)
 {
     const uint32_t lane = threadIdx.x & 63;
     // uniform across the wavefront: task fields and round records become
@@ -238,12 +238,9 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t *acc = lds;                                  // kRowBlock accumulators
     uint64_t *tab = lds + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
-    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
-        reinterpret_cast<ulonglong2 *>(acc)[i] = make_ulonglong2(0ull, 0ull);
-    __syncthreads();
-    const SpTask tk = tasks[tile * WAVES + wave];
+    const SpTask tk = wg_tasks[wave];
     const uint32_t n = tk.n_rounds;
-    if (n > 0) {
+    {
         const SpRound *rr = rounds + tk.round0;
 
         struct Stage {
@@ -346,11 +343,19 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
         // last round is processed again (fetch clamps to it), which changes
         // nothing: its tables are rebuilt with the same contents and OR is
         // idempotent.
+        // the first rounds' loads are issued before the accumulators are
+        // cleared, so that their latency overlaps the clearing and the
+        // barrier
         Stage st[kStages];
+        if (n > 0) {
 #pragma unroll
-        for (int k = 0; k < kStages; ++k) st[k].rec = load_rec(k);
+            for (int k = 0; k < kStages; ++k) st[k].rec = load_rec(k);
 #pragma unroll
-        for (int k = 0; k + 1 < kStages; ++k) fetch(st[k], k);
+            for (int k = 0; k + 1 < kStages; ++k) fetch(st[k], k);
+        }
+        for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
+            reinterpret_cast<ulonglong2 *>(acc)[i] = make_ulonglong2(0ull, 0ull);
+        __syncthreads();
         for (uint32_t i = 0; i < n; i += kStages) {
 #pragma unroll
             for (int k = 0; k < kStages; ++k) {
@@ -368,18 +373,18 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ tasks, cons
     }
 }
 
-// One workgroup per tile of a single frame, workgroup b running tile
-// block_tile[b].  Partials P[tile][kRowBlock].
+// One workgroup per tile of a single frame: workgroup b runs tile
+// block_tile[b], whose tasks tasks_launch holds at b * WAVES (no dependent
+// load before the first task).  Partials P[tile][kRowBlock].
 template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
-k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks,
+k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks_launch,
               const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg,
-              uint64_t *__restrict__ P)
+              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg, uint64_t *__restrict__ P)
 {
     extern __shared__ uint64_t lds[];
-    const uint32_t tile = block_tile[blockIdx.x];
-    tile_body<WAVES>(tasks, rounds, sp_row, sp_val, Tg, 256, tile, P + (uint64_t)tile * kRowBlock, lds);
+    tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256,
+                     P + (uint64_t)block_tile[blockIdx.x] * kRowBlock, lds);
 }
 
 // One workgroup per (pass, tile, lane group) of a batch.  The pass's nibble
@@ -391,8 +396,8 @@ k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__rest
     extern __shared__ uint64_t lds[];
     const TileItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    tile_body<WAVES>(g.sp_tasks, g.sp_rounds, g.sp_row, g.sp_val, g.Ow + (uint64_t)it.gi * 256,
-                     (uint64_t)g.G64 * 256, it.tile,
+    tile_body<WAVES>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
+                     g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256,
                      g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
 }
 
@@ -705,6 +710,7 @@ SparseLayout::~SparseLayout()
         (void)hipFree(t.rounds);
         (void)hipFree(t.rb_tile);
         (void)hipFree(t.block_tile);
+        (void)hipFree(t.tasks_launch);
     }
 }
 
@@ -740,7 +746,13 @@ static lbl_status upload_tiling(const TilingHost &h, SpTiling *t, size_t *bytes)
     LBL_HIP_TRY(hipMalloc(&t->block_tile, std::max<size_t>(h.block_tile.size(), 1) * sizeof(uint32_t)));
     LBL_HIP_TRY(hipMemcpy(t->block_tile, h.block_tile.data(), h.block_tile.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice));
-    *bytes += h.tasks.size() * sizeof(SpTask) + h.rounds.size() * sizeof(SpRound) +
+    std::vector<SpTask> launch(h.tasks.size());
+    for (size_t b = 0; b < h.block_tile.size(); ++b)
+        for (uint32_t w = 0; w < kTileWaves; ++w)
+            launch[b * kTileWaves + w] = h.tasks[(size_t)h.block_tile[b] * kTileWaves + w];
+    LBL_HIP_TRY(hipMalloc(&t->tasks_launch, launch.size() * sizeof(SpTask)));
+    LBL_HIP_TRY(hipMemcpy(t->tasks_launch, launch.data(), launch.size() * sizeof(SpTask), hipMemcpyHostToDevice));
+    *bytes += 2 * h.tasks.size() * sizeof(SpTask) + h.rounds.size() * sizeof(SpRound) +
               (h.rb_tile.size() + h.block_tile.size()) * sizeof(uint32_t);
     return LBL_OK;
 }
@@ -862,7 +874,7 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     span_end(spn, s, 0);
     spn = span_begin(s);
     hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.block_tile,
-                       tl.tasks, tl.rounds, sp.row, sp.val, Tg, P);
+                       tl.tasks_launch, tl.rounds, sp.row, sp.val, Tg, P);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
     spn = span_begin(s);
