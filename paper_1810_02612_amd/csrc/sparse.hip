@@ -408,11 +408,15 @@ __device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P,
     const uint64_t rb = t / kRowBlock, loc = t % kRowBlock;
     const uint32_t k0 = rb_tile[rb], k1 = rb_tile[rb + 1];
     uint64_t bits = 0;
-    uint32_t k = k0;
-    for (; k + 4 <= k1; k += 4)
-        bits |= P[(uint64_t)k * kRowBlock + loc] | P[(uint64_t)(k + 1) * kRowBlock + loc] |
-                P[(uint64_t)(k + 2) * kRowBlock + loc] | P[(uint64_t)(k + 3) * kRowBlock + loc];
-    for (; k < k1; ++k) bits |= P[(uint64_t)k * kRowBlock + loc];
+    // sixteen loads in flight at a time: indices past the block's last tile
+    // read that tile again, which leaves the OR unchanged
+    for (uint32_t kb = k0; kb < k1; kb += 16) {
+        uint64_t v[16];
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) v[j] = P[(uint64_t)min(kb + j, k1 - 1) * kRowBlock + loc];
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) bits |= v[j];
+    }
     return bits;
 }
 
