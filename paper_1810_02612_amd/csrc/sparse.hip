@@ -10,8 +10,9 @@
 // block and shared by every trajectory of the block that crosses it.
 //
 // Tilings (built on the host at load time).  A row block's entries are cut
-// into wavefront tasks of equal cost (entries plus a charge per segment
-// started), kTileWaves tasks to a tile (one workgroup).  A task is walked in
+// into wavefront tasks by the cost of the rounds walked (a round plus a
+// charge per table copy), kTileWaves tasks to a tile (one workgroup), each
+// task sized to its wavefront's issue share (wave_share).  A task is walked in
 // rounds of 64 consecutive entries, one per lane; a round whose entries
 // span more than two segments is split so that each round touches at most
 // two.  Each round carries which lanes are active, which lanes fall in its
@@ -28,8 +29,10 @@
 //                  active lane ORs the 16 entries selected by the nibbles of
 //                  its word value (the labels of that (row, word) pair for up
 //                  to 64 propositions) into the tile's per-row accumulators
-//                  with an LDS atomic.  The accumulators are written once per
-//                  tile as its partial labels.
+//                  with an LDS atomic.  Three rounds are in flight per
+//                  wavefront (loads issued ahead of the round processed).
+//                  The accumulators are written once per tile as its partial
+//                  labels.
 //   k_combine      OR of a row's partials over the tiles of its row block ->
 //                  the caller's L bytes (0/1).
 // OR is idempotent and commutative, so neither the order of the LDS atomics
