@@ -62,6 +62,9 @@ def _bind(path: str):
     lib.oracle_label_dense.argtypes = [u8, ctypes.c_uint64, ctypes.c_uint64, u8, ctypes.c_uint32, u8]
     lib.oracle_zorder.restype = ctypes.c_uint64
     lib.oracle_zorder.argtypes = [ctypes.c_int, ctypes.c_int, d, d, d]
+    lib.oracle_raster_shapes.restype = ctypes.c_int
+    lib.oracle_raster_shapes.argtypes = [u32, u32, d, d, d, d, ctypes.c_uint64, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32, u8]
     return lib
 
 
@@ -120,3 +123,22 @@ def zorder(x, lo, hi, d: int) -> int:
     k = len(x)
     return int(lib.oracle_zorder(k, d, _p(x, ctypes.c_double), _p(lo, ctypes.c_double),
                                  _p(hi, ctypes.c_double)))
+
+
+def raster_shapes(kind, prop, cx, cy, a, b, nx: int, ny: int, cell: float, n_props: int) -> np.ndarray:
+    """O (n_cells x n_props, row-major cells, 0/1) of proposition shapes by the
+    Sec. 4.1 encoding read as positive-area overlap (every cell x every shape)."""
+    lib = _load()
+    kind = np.ascontiguousarray(kind, np.uint32)
+    prop = np.ascontiguousarray(prop, np.uint32)
+    cx, cy, a, b = (np.ascontiguousarray(x, np.float64) for x in (cx, cy, a, b))
+    n = len(kind)
+    if not all(len(x) == n for x in (prop, cx, cy, a, b)):
+        raise ValueError("shape arrays differ in length")
+    O = np.empty((nx * ny, n_props), np.uint8)
+    rc = lib.oracle_raster_shapes(_p(kind, ctypes.c_uint32), _p(prop, ctypes.c_uint32), _p(cx, ctypes.c_double),
+                                  _p(cy, ctypes.c_double), _p(a, ctypes.c_double), _p(b, ctypes.c_double), n,
+                                  nx, ny, float(cell), n_props, _p(O, ctypes.c_uint8))
+    if rc != 0:
+        raise ValueError("invalid shape kind or proposition index")
+    return O

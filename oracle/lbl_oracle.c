@@ -154,3 +154,55 @@ uint64_t oracle_zorder(int k, int d, const double *x, const double *lo, const do
     }
     return n;
 }
+
+/*
+ * Binary-vector encoding of proposition regions (Sec. 4.1): entry i of a
+ * proposition's vector is 1 iff its region intersects cell i of the
+ * partition.  "Intersects" is read as an overlap of positive area with the
+ * closed cell square, so a region that only touches a cell's boundary does
+ * not mark it.  A region is a union of shapes; shape s belongs to
+ * proposition prop[s] and is
+ *   kind 0: the axis-aligned rectangle with centre (cx, cy) and half sizes
+ *           (a, b), or
+ *   kind 1: the disc with centre (cx, cy) and radius a.
+ * Cells form an nx x ny grid of side cell, cell (ix, iy) the square
+ * [x0, x0 + cell] x [y0, y0 + cell] with x0 = ix * cell, y0 = iy * cell,
+ * stored row-major (c = iy * nx + ix).  O[c * n_props + p] is set to 1 iff
+ * some shape of proposition p meets cell c, else 0.
+ *
+ * Every cell is tested against every shape (no bounding boxes):
+ *   rectangle: the two intervals on each axis overlap with positive length,
+ *              min of the upper ends minus max of the lower ends > 0;
+ *   disc:      the square's point nearest the centre lies at a distance
+ *              below the radius (squared distance < a * a).
+ * Returns 0, or -1 for a kind other than 0 or 1 or a prop >= n_props.
+ */
+int oracle_raster_shapes(const uint32_t *kind, const uint32_t *prop, const double *cx, const double *cy,
+                         const double *a, const double *b, uint64_t n_shapes, uint32_t nx, uint32_t ny,
+                         double cell, uint32_t n_props, uint8_t *O)
+{
+    for (uint64_t s = 0; s < n_shapes; ++s)
+        if (kind[s] > 1 || prop[s] >= n_props) return -1;
+    for (uint32_t iy = 0; iy < ny; ++iy) {
+        const double y0 = (double)iy * cell, y1 = y0 + cell;
+        for (uint32_t ix = 0; ix < nx; ++ix) {
+            const double x0 = (double)ix * cell, x1 = x0 + cell;
+            uint8_t *o = O + ((uint64_t)iy * nx + ix) * n_props;
+            for (uint32_t p = 0; p < n_props; ++p) o[p] = 0;
+            for (uint64_t s = 0; s < n_shapes; ++s) {
+                int hit;
+                if (kind[s] == 0) {
+                    const double ox = fmin(x1, cx[s] + a[s]) - fmax(x0, cx[s] - a[s]);
+                    const double oy = fmin(y1, cy[s] + b[s]) - fmax(y0, cy[s] - b[s]);
+                    hit = ox > 0.0 && oy > 0.0;
+                } else {
+                    const double qx = fmin(fmax(cx[s], x0), x1), qy = fmin(fmax(cy[s], y0), y1);
+                    const double ex = cx[s] - qx, ey = cy[s] - qy;
+                    hit = ex * ex + ey * ey < a[s] * a[s];
+                }
+                if (hit) o[prop[s]] = 1;
+            }
+        }
+    }
+    return 0;
+}
