@@ -184,6 +184,44 @@ typedef struct {
 lbl_status lbl_label_batch(const lbl_job *jobs, size_t n_jobs, uint32_t flags, void *hip_stream);
 
 /*
+ * Proposition regions of one frame, rasterized on the device into O
+ * (Sec. 4.1: the binary vector of a region has a 1 at every cell the region
+ * intersects; "intersects" read as an overlap of positive area with the
+ * closed cell square, so touching a cell's boundary does not mark it).
+ *
+ * A region is a union of shapes in workspace coordinates (metres, the grid's
+ * origin at (0, 0)); shape i belongs to proposition prop:
+ *   LBL_SHAPE_RECT  axis-aligned rectangle, centre (cx, cy), half sizes (a, b);
+ *   LBL_SHAPE_DISC  disc, centre (cx, cy), radius a (b unused).
+ * Cell (ix, iy) is the square [ix * cell_m, ix * cell_m + cell_m] x
+ * [iy * cell_m, iy * cell_m + cell_m], computed in double precision, and O is
+ * written as lbl_label_frame reads it: n_cells x n_props bytes, cells
+ * row-major (iy * nx + ix), exactly 0 or 1.  cell_m is given here in double
+ * precision (the grid's float cell_m is informational).
+ *
+ * shapes: host array of n_shapes entries, read during the call (the caller
+ * may reuse it on return); O: device buffer, written stream-ordered on
+ * hip_stream (every byte, including those of propositions without shapes).
+ *
+ * Errors: LBL_EINVAL for a null grid, O, or shapes with n_shapes > 0;
+ * n_props outside [1, 64]; cell_m not finite and positive; a kind other than
+ * the two above; prop >= n_props; a coordinate or size not finite, or a
+ * negative size.  LBL_EDEVICE for a HIP error.
+ */
+#define LBL_SHAPE_RECT 0u
+#define LBL_SHAPE_DISC 1u
+
+typedef struct {
+    uint32_t kind; /* LBL_SHAPE_RECT or LBL_SHAPE_DISC */
+    uint32_t prop; /* proposition index, < n_props */
+    double cx, cy; /* centre, metres */
+    double a, b;   /* half sizes (rectangle) or radius a (disc) */
+} lbl_shape;
+
+lbl_status lbl_raster_frame(const lbl_grid *grid, double cell_m, const lbl_shape *shapes, uint64_t n_shapes,
+                            uint32_t n_props, uint8_t *O, void *hip_stream);
+
+/*
  * Autotuner.  lbl_tune times the candidate kernels and tile shapes for the
  * abstraction's shape class (row count, word count, proposition count, T word
  * density) on one frame and records the fastest; LBL_KERNEL_AUTO then uses

@@ -37,6 +37,7 @@ EXPORTS = (
     "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_batch", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
     "lbl_serve_start", "lbl_serve_submit", "lbl_serve_wait", "lbl_serve_stats_get", "lbl_serve_stop",
     "lbl_cell_position", "lbl_last_error", "lbl_version", "lbl_profile_enable", "lbl_profile_read",
+    "lbl_raster_frame",
 )
 
 
@@ -125,6 +126,7 @@ def lib():
         "lbl_cell_position": [ctypes.POINTER(Grid), u32, ctypes.POINTER(u32), ctypes.POINTER(u32)],
         "lbl_profile_enable": [ctypes.c_int],
         "lbl_profile_read": [ctypes.POINTER(Profile)],
+        "lbl_raster_frame": [ctypes.POINTER(Grid), ctypes.c_double, vp, u64, u32, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -223,6 +225,30 @@ def abstraction_info(a: int) -> dict:
 
 def label_frame(a: int, O, n_props: int, L, flags: int = 0, stream=None) -> None:
     _check(lib().lbl_label_frame(a, _addr(O), n_props, _addr(L), flags, _stream(stream)))
+
+
+SHAPE_RECT, SHAPE_DISC = 0, 1
+# lbl_shape: kind, prop, cx, cy, a, b (40 bytes, no padding)
+SHAPE_DTYPE = np.dtype([("kind", "<u4"), ("prop", "<u4"), ("cx", "<f8"), ("cy", "<f8"), ("a", "<f8"), ("b", "<f8")])
+
+
+def shapes_array(kind, prop, cx, cy, a, b) -> np.ndarray:
+    """Host lbl_shape records from parallel arrays."""
+    n = len(kind)
+    out = np.zeros(n, SHAPE_DTYPE)
+    for name, v in (("kind", kind), ("prop", prop), ("cx", cx), ("cy", cy), ("a", a), ("b", b)):
+        out[name] = np.asarray(v)
+    return out
+
+
+def raster_frame(nx: int, ny: int, cell_m: float, shapes: np.ndarray, n_props: int, O, stream=None) -> None:
+    """Rasterize proposition shapes (a SHAPE_DTYPE host array) into the device
+    frame O (n_cells x n_props bytes, row-major cells)."""
+    shapes = np.ascontiguousarray(shapes, SHAPE_DTYPE)
+    g = _grid(nx, ny, cell_m)
+    ptr = shapes.ctypes.data if len(shapes) else None
+    _check(lib().lbl_raster_frame(ctypes.byref(g), float(cell_m), ptr, len(shapes), n_props, _addr(O),
+                                  _stream(stream)))
 
 
 def label_batch(jobs, flags: int = 0, stream=None) -> None:
