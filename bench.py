@@ -52,6 +52,7 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the kernel x density sweep")
     p.add_argument("--sweep-steps", type=int, default=10)
     p.add_argument("--no-pcie", action="store_true")
+    p.add_argument("--no-raster", action="store_true", help="skip the proposition rasterizer leg")
     p.add_argument("--no-batch", action="store_true", help="skip the six-abstraction batched run")
     p.add_argument("--batch-reps", type=int, default=10)
     p.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -382,6 +383,38 @@ def main():
         dt = (time.perf_counter() - t) / n
         out["pcie_inclusive"] = {"ms_per_frame": 1000 * dt, "pairs_per_s": pairs / dt,
                                  "note": "host O in and host L out per frame; not the headline value"}
+
+    if not args.no_raster:
+        # the frames' proposition shapes rasterized on the device (the step
+        # before the labeling path), then shapes -> O -> L per frame; the
+        # rasterized frames are the ones the headline labels
+        shapes = []
+        for f in range(args.frames):
+            sh = gen.frame_shapes(3, a.grid, n_props, f, rho=args.rho)
+            shapes.append(lbl.shapes_array(sh.kind, sh.prop, sh.cx, sh.cy, sh.a, sh.b))
+        Or = torch.empty((a.grid.n_cells, n_props), dtype=torch.uint8, device="cuda")
+        lbl.raster_frame(a.grid.n, a.grid.n, a.grid.res, shapes[0], n_props, Or, stream=stream)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(Or, Os[0]))
+        n = args.steps
+        t = time.perf_counter()
+        for k in range(n):
+            lbl.raster_frame(a.grid.n, a.grid.n, a.grid.res, shapes[k % len(shapes)], n_props, Or, stream=stream)
+        torch.cuda.synchronize()
+        dt_r = (time.perf_counter() - t) / n
+        t = time.perf_counter()
+        for k in range(n):
+            lbl.raster_frame(a.grid.n, a.grid.n, a.grid.res, shapes[k % len(shapes)], n_props, Or, stream=stream)
+            lbl.label_frame(h, Or, n_props, L, flags=flags, stream=stream)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t) / n
+        o_bytes = a.grid.n_cells * n_props
+        out["raster"] = {"shapes_per_frame": float(np.mean([len(x) for x in shapes])), "ms_per_frame": 1000 * dt_r,
+                         "o_bytes": o_bytes, "o_written_gb_per_s": o_bytes / dt_r / 1e9,
+                         "equals_headline_frames": same, "shapes_to_L_ms_per_frame": 1000 * dt_s,
+                         "shapes_to_L_pairs_per_s": pairs / dt_s,
+                         "note": "wall time per call, host validation and the shape upload included"}
+        log("raster", out["raster"])
 
     if not args.no_sweep:
         sweep = []
