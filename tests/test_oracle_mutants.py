@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_raster as rpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lbl_oracle.c")
 
@@ -27,6 +28,31 @@ MUTANTS = {
     "zorder_step": ("(i - 1) / k + 2", "i / k + 2"),
     "zorder_msb": ("(uint64_t)1 << (d - i)", "(uint64_t)1 << (i - 1)"),
 }
+
+
+# mistakes in the proposition encoding (oracle_raster_shapes)
+RASTER_MUTANTS = {
+    "disc_closed": ("ex * ex + ey * ey < a[s] * a[s]", "ex * ex + ey * ey <= a[s] * a[s]"),
+    "disc_radius_unsquared": ("ey * ey < a[s] * a[s]", "ey * ey < a[s]"),
+    "disc_drops_y": ("const double ex = cx[s] - qx, ey = cy[s] - qy;", "const double ex = cx[s] - qx, ey = 0.0;"),
+    "rect_closed": ("hit = ox > 0.0 && oy > 0.0;", "hit = ox >= 0.0 && oy >= 0.0;"),
+    "rect_height_from_a": ("fmin(y1, cy[s] + b[s])", "fmin(y1, cy[s] + a[s])"),
+    "cell_without_height": ("y1 = y0 + cell;", "y1 = y0;"),
+    "cells_transposed": ("((uint64_t)iy * nx + ix) * n_props", "((uint64_t)ix * ny + iy) * n_props"),
+    "last_shape_dropped": ("for (uint64_t s = 0; s < n_shapes; ++s) {", "for (uint64_t s = 0; s + 1 < n_shapes; ++s) {"),
+}
+
+
+def run_raster_pins():
+    for args in [(1, 64, 0.5, 8, 0), (2, 128, 0.25, 16, 2)]:
+        rpins.test_matches_generator_rasterizer(*args)
+    rpins.test_grid_aligned_rectangle_marks_enclosed_cells()
+    rpins.test_disc_on_corner_marks_four_cells()
+    rpins.test_small_disc_inside_one_cell()
+    rpins.test_touching_is_not_intersecting()
+    rpins.test_outside_and_clipped()
+    rpins.test_sampled_brute_force()
+    rpins.test_union_is_or()
 
 
 def run_pins():
@@ -60,5 +86,24 @@ def test_mutant_is_caught(name, tmp_path):
         oracle._lib = saved
 
 
+@pytest.mark.parametrize("name", sorted(RASTER_MUTANTS))
+def test_raster_mutant_is_caught(name, tmp_path):
+    old, new = RASTER_MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-o", str(so), str(path), "-lm", "-lpthread"])
+    saved = oracle._lib
+    oracle._lib = oracle._bind(str(so))
+    try:
+        with pytest.raises((AssertionError, ValueError)):
+            run_raster_pins()
+    finally:
+        oracle._lib = saved
+
+
 def test_unmutated_passes():
     run_pins()
+    run_raster_pins()
