@@ -97,3 +97,35 @@ def test_batch_and_serve_reject_bad_arguments():
         lbl.label_batch([], 0)
     with pytest.raises(lbl.LblError):
         lbl.serve_start(max_batch_frames=0)
+
+
+def test_raster_rejects_bad_arguments_without_a_device():
+    L = lbl.lib()
+    g = lbl.Grid(16, 16, 0.5, 0)
+    fake_O = ctypes.c_void_p(0x1000)  # validation fails before any device access
+    good = lbl.shapes_array([0], [0], [1.0], [1.0], [0.5], [0.5])
+
+    def call(shapes, n_props=4, cell=0.5, grid=g, O=fake_O, n=None):
+        ptr = shapes.ctypes.data if shapes is not None and len(shapes) else None
+        n = len(shapes) if n is None else n
+        return L.lbl_raster_frame(ctypes.byref(grid) if grid is not None else None, cell, ptr, n, n_props, O, None)
+
+    cases = [
+        lambda: call(good, grid=None),
+        lambda: call(good, O=None),
+        lambda: call(None, n=3),
+        lambda: call(good, grid=lbl.Grid(12, 16, 0.5, 0)),
+        lambda: call(good, grid=lbl.Grid(16, 16, 0.5, 1)),
+        lambda: call(good, n_props=0),
+        lambda: call(good, n_props=65),
+        lambda: call(good, cell=0.0),
+        lambda: call(good, cell=float("nan")),
+        lambda: call(lbl.shapes_array([2], [0], [1.0], [1.0], [0.5], [0.5])),
+        lambda: call(lbl.shapes_array([0], [4], [1.0], [1.0], [0.5], [0.5])),
+        lambda: call(lbl.shapes_array([1], [0], [float("inf")], [1.0], [0.5], [0.0])),
+        lambda: call(lbl.shapes_array([1], [0], [1.0], [1.0], [-0.5], [0.0])),
+        lambda: call(lbl.shapes_array([0], [0], [1.0], [1.0], [0.5], [-0.5])),
+    ]
+    for i, c in enumerate(cases):
+        assert c() == lbl.EINVAL, i
+        assert lbl.last_error(), i
