@@ -70,6 +70,13 @@ typedef struct {
 #define LBL_LOAD_KEEP_INT8 0x1u    /* also keep an int8 copy of T (N_t x N_c bytes) */
 #define LBL_LOAD_INPUT_DEVICE 0x2u /* the input arrays are device pointers */
 #define LBL_LOAD_NO_SPARSE 0x4u    /* do not build the sparse tiled layout */
+#define LBL_LOAD_SPARSE_ONLY 0x8u  /* keep only the sparse tiled layout: the bitpacked T
+                                     is built a run of row blocks at a time (about
+                                     4 GiB) and dropped, so abstractions larger than
+                                     device memory in bitpacked form fit; only
+                                     LBL_KERNEL_SPARSE (or AUTO) can label them.
+                                     lbl_load_abstraction only; not with
+                                     LBL_LOAD_KEEP_INT8 or LBL_LOAD_NO_SPARSE */
 
 /* ---- flags for lbl_label_frame / lbl_label_batch ---------------------- */
 #define LBL_HOST_PTRS 0x1u      /* O and L are host pointers; the call is synchronous */
@@ -95,10 +102,16 @@ typedef struct {
  * handle owns the device copy until lbl_free_abstraction.  The call is
  * synchronous and uses the current HIP device.
  *
+ * With LBL_LOAD_SPARSE_ONLY the device holds only the sparse tiled layout
+ * (non-zero 64-cell words of T, 10 bytes each, and its tilings): a workspace
+ * of 2^21 cells and a million rows, 288 GB as bitpacked rows, takes about a
+ * gigabyte.  Labels are identical to those of a full load.
+ *
  * Errors: LBL_EINVAL for a null pointer, n_traj == 0, nx or ny not a positive
- * multiple of 8, reserved != 0, row_ptr[0] != 0 or decreasing, or a column id
- * >= nx * ny; LBL_ENOMEM if device memory runs out; LBL_EDEVICE on a HIP
- * error.
+ * multiple of 8, reserved != 0, row_ptr[0] != 0 or decreasing, a column id
+ * >= nx * ny, an unknown or contradictory flag, or LBL_LOAD_SPARSE_ONLY with
+ * 2^32 rows or more; LBL_ENOMEM if device memory runs out; LBL_EDEVICE on a
+ * HIP error.
  */
 lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uint64_t *row_ptr,
                                 const uint32_t *col_idx, uint32_t flags, lbl_abs_t *out);
@@ -149,7 +162,9 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);
  * and synchronizes that stream; later calls do not.
  *
  * Errors: LBL_EINVAL for a null handle or pointer, n_props outside [1, 64],
- * an unknown kernel flag, or LBL_KERNEL_MFMA_I8 without an int8 copy of T.
+ * an unknown kernel flag, LBL_KERNEL_MFMA_I8 without an int8 copy of T, or
+ * LBL_KERNEL_BITS / LBL_KERNEL_MFMA on an abstraction loaded with
+ * LBL_LOAD_SPARSE_ONLY (no bitpacked T).
  */
 lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint8_t *L,
                            uint32_t flags, void *hip_stream);
@@ -169,8 +184,10 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
  * (up to 8 graphs are cached; the oldest is released after a device
  * synchronization).  Results are identical to labeling each job alone.
  *
- * Errors: as lbl_label_frame for every job, plus LBL_EINVAL for n_jobs == 0
- * or nonzero flags.
+ * Errors: as lbl_label_frame for every job, plus LBL_EINVAL for n_jobs == 0,
+ * nonzero flags, or a batch mixing an abstraction without the sparse layout
+ * (LBL_LOAD_NO_SPARSE) and one without the bitpacked T
+ * (LBL_LOAD_SPARSE_ONLY): such a batch has no common kernel.
  */
 typedef struct {
     lbl_abs_t a;

@@ -102,7 +102,7 @@ static lbl_status check_grid(const lbl_grid *g)
 }
 
 // Allocate the abstraction's device tables and the zeroed bitpacked T.
-static lbl_status abs_alloc(const lbl_grid *g, uint64_t n_traj, std::unique_ptr<lbl_abs> &a)
+static lbl_status abs_alloc(const lbl_grid *g, uint64_t n_traj, std::unique_ptr<lbl_abs> &a, bool dense = true)
 {
     a.reset(new lbl_abs());
     LBL_HIP_TRY(hipGetDevice(&a->device));
@@ -120,6 +120,7 @@ static lbl_status abs_alloc(const lbl_grid *g, uint64_t n_traj, std::unique_ptr<
                           a->order.tile_word.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     LBL_HIP_TRY(hipMemcpy(a->d_word_cell, a->order.word_cell.data(),
                           a->order.word_cell.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!dense) return LBL_OK;
     const size_t bytes = (size_t)n_traj * a->row_stride * sizeof(uint64_t);
     LBL_HIP_TRY(hipMalloc(&a->T_bits, bytes));
     LBL_HIP_TRY(hipMemset(a->T_bits, 0, bytes));
@@ -218,7 +219,12 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
     *out = nullptr;
     LBL_REQUIRE(row_ptr != nullptr, "row_ptr is null");
     LBL_REQUIRE(n_traj > 0, "n_traj must be positive");
-    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE | LBL_LOAD_NO_SPARSE)) == 0, "unknown load flag");
+    LBL_REQUIRE((flags & ~(LBL_LOAD_KEEP_INT8 | LBL_LOAD_INPUT_DEVICE | LBL_LOAD_NO_SPARSE | LBL_LOAD_SPARSE_ONLY)) == 0,
+                "unknown load flag");
+    const bool sparse_only = flags & LBL_LOAD_SPARSE_ONLY;
+    LBL_REQUIRE(!sparse_only || !(flags & (LBL_LOAD_KEEP_INT8 | LBL_LOAD_NO_SPARSE)),
+                "LBL_LOAD_SPARSE_ONLY excludes LBL_LOAD_KEEP_INT8 and LBL_LOAD_NO_SPARSE");
+    LBL_REQUIRE(!sparse_only || n_traj < (1ull << 32), "LBL_LOAD_SPARSE_ONLY needs fewer than 2^32 rows");
     const bool dev_in = flags & LBL_LOAD_INPUT_DEVICE;
 
     // row pointers on the host for validation and chunking
@@ -235,7 +241,7 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
     LBL_REQUIRE(nnz == 0 || col_idx != nullptr, "col_idx is null");
 
     std::unique_ptr<lbl_abs> tmp;
-    st = abs_alloc(grid, n_traj, tmp);
+    st = abs_alloc(grid, n_traj, tmp, !sparse_only);
     std::unique_ptr<lbl_abs, AbsDeleter> a(tmp.release());
     if (st != LBL_OK) return st;
 
@@ -244,42 +250,90 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
     std::unique_ptr<uint32_t, decltype(&hipFree)> bad_guard(d_bad, &hipFree);
     LBL_HIP_TRY(hipMemset(d_bad, 0, sizeof(uint32_t)));
 
-    if (dev_in) {
-        LBL_HIP_TRY(launch_pack_csr(a->T_bits, a->row_stride, row_ptr, 0, n_traj, col_idx, 0, a->d_tile_word,
-                                    a->nx, a->n_cells, d_bad, nullptr));
-    } else {
-        // upload in chunks of whole rows, at most ~64M column ids each
-        const uint64_t chunk_cap = 64ull << 20;
-        uint64_t max_rows = 0, max_cols = 0;
-        for (uint64_t t0 = 0; t0 < n_traj;) {
-            uint64_t t1 = t0 + 1;
-            while (t1 < n_traj && rp[t1 + 1] - rp[t0] <= chunk_cap && t1 - t0 < (1ull << 20)) ++t1;
-            max_rows = std::max(max_rows, t1 - t0);
-            max_cols = std::max(max_cols, rp[t1] - rp[t0]);
-            t0 = t1;
+    // host input is uploaded in chunks of whole rows, at most ~64M column ids
+    // and 2^20 rows each (one row may exceed the column bound)
+    const uint64_t chunk_cap = 64ull << 20, chunk_rows = 1ull << 20;
+    uint64_t *d_rp = nullptr;
+    uint32_t *d_ci = nullptr;
+    std::unique_ptr<uint64_t, decltype(&hipFree)> rp_guard(nullptr, &hipFree);
+    std::unique_ptr<uint32_t, decltype(&hipFree)> ci_guard(nullptr, &hipFree);
+    if (!dev_in) {
+        uint64_t max_row = 0;
+        for (uint64_t t = 0; t < n_traj; ++t) max_row = std::max(max_row, rp[t + 1] - rp[t]);
+        LBL_HIP_TRY(hipMalloc(&d_rp, (std::min(n_traj, chunk_rows) + 1) * sizeof(uint64_t)));
+        rp_guard.reset(d_rp);
+        LBL_HIP_TRY(hipMalloc(&d_ci, std::max<uint64_t>(std::min(nnz, std::max(chunk_cap, max_row)), 1) *
+                                         sizeof(uint32_t)));
+        ci_guard.reset(d_ci);
+    }
+    // Sets the cells of rows [t_begin, t_end) in the zeroed bitpacked rows T,
+    // whose first row is row `first`.
+    auto pack_rows = [&](uint64_t *T, uint64_t first, uint64_t t_begin, uint64_t t_end) -> lbl_status {
+        if (dev_in) {
+            LBL_HIP_TRY(launch_pack_csr(T, a->row_stride, row_ptr + t_begin, t_begin - first, t_end - t_begin,
+                                        col_idx, 0, a->d_tile_word, a->nx, a->n_cells, d_bad, nullptr));
+            LBL_HIP_TRY(hipDeviceSynchronize());
+            return LBL_OK;
         }
-        uint64_t *d_rp = nullptr;
-        uint32_t *d_ci = nullptr;
-        LBL_HIP_TRY(hipMalloc(&d_rp, (max_rows + 1) * sizeof(uint64_t)));
-        std::unique_ptr<uint64_t, decltype(&hipFree)> rp_guard(d_rp, &hipFree);
-        LBL_HIP_TRY(hipMalloc(&d_ci, std::max<uint64_t>(max_cols, 1) * sizeof(uint32_t)));
-        std::unique_ptr<uint32_t, decltype(&hipFree)> ci_guard(d_ci, &hipFree);
-        for (uint64_t t0 = 0; t0 < n_traj;) {
+        for (uint64_t t0 = t_begin; t0 < t_end;) {
             uint64_t t1 = t0 + 1;
-            while (t1 < n_traj && rp[t1 + 1] - rp[t0] <= chunk_cap && t1 - t0 < (1ull << 20)) ++t1;
+            while (t1 < t_end && rp[t1 + 1] - rp[t0] <= chunk_cap && t1 - t0 < chunk_rows) ++t1;
             const uint64_t nc = rp[t1] - rp[t0];
             LBL_HIP_TRY(hipMemcpy(d_rp, rp + t0, (t1 - t0 + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
             if (nc) LBL_HIP_TRY(hipMemcpy(d_ci, col_idx + rp[t0], nc * sizeof(uint32_t), hipMemcpyHostToDevice));
-            LBL_HIP_TRY(launch_pack_csr(a->T_bits, a->row_stride, d_rp, t0, t1 - t0, d_ci, rp[t0],
-                                        a->d_tile_word, a->nx, a->n_cells, d_bad, nullptr));
+            LBL_HIP_TRY(launch_pack_csr(T, a->row_stride, d_rp, t0 - first, t1 - t0, d_ci, rp[t0], a->d_tile_word,
+                                        a->nx, a->n_cells, d_bad, nullptr));
             LBL_HIP_TRY(hipDeviceSynchronize());
             t0 = t1;
         }
+        return LBL_OK;
+    };
+    auto check_bad = [&]() -> lbl_status {
+        uint32_t h_bad = 0;
+        LBL_HIP_TRY(hipMemcpy(&h_bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        LBL_REQUIRE(h_bad == 0, "col_idx holds a cell id >= nx * ny");
+        return LBL_OK;
+    };
+
+    if (!sparse_only) {
+        st = pack_rows(a->T_bits, 0, 0, n_traj);
+        if (st == LBL_OK) st = check_bad();
+        if (st == LBL_OK) st = abs_finish(a.get(), flags);
+        if (st != LBL_OK) return st;
+        *out = a.release();
+        return LBL_OK;
     }
-    uint32_t h_bad = 0;
-    LBL_HIP_TRY(hipMemcpy(&h_bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    LBL_REQUIRE(h_bad == 0, "col_idx holds a cell id >= nx * ny");
-    st = abs_finish(a.get(), flags);
+
+    // Sparse only: runs of whole row blocks (about 4 GiB of bitpacked rows
+    // each) are packed into one reused buffer and turned into entries.
+    const uint64_t row_bytes = (uint64_t)a->row_stride * sizeof(uint64_t);
+    const uint64_t run = kRowBlock * std::max<uint64_t>(1, (4ull << 30) / (row_bytes * kRowBlock));
+    uint64_t *d_T = nullptr;
+    LBL_HIP_TRY(hipMalloc(&d_T, std::min(run, n_traj) * row_bytes));
+    std::unique_ptr<uint64_t, decltype(&hipFree)> T_guard(d_T, &hipFree);
+    unsigned long long *d_cnt = nullptr;
+    LBL_HIP_TRY(hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
+    std::unique_ptr<unsigned long long, decltype(&hipFree)> cnt_guard(d_cnt, &hipFree);
+    LBL_HIP_TRY(hipMemset(d_cnt, 0, 2 * sizeof(unsigned long long)));
+    std::vector<SparsePart> parts;
+    for (uint64_t r0 = 0; r0 < n_traj; r0 += run) {
+        const uint64_t r1 = std::min(n_traj, r0 + run);
+        LBL_HIP_TRY(hipMemset(d_T, 0, (r1 - r0) * row_bytes));
+        st = pack_rows(d_T, r0, r0, r1);
+        if (st != LBL_OK) return st;
+        LBL_HIP_TRY(launch_count_words(d_T, a->row_stride, r1 - r0, a->n_words, d_cnt, nullptr));
+        parts.emplace_back();
+        st = sparse_part(d_T, a->row_stride, r1 - r0, a->n_words, &parts.back());
+        if (st != LBL_OK) return st;
+    }
+    st = check_bad();
+    if (st != LBL_OK) return st;
+    unsigned long long h[2] = {0, 0};
+    LBL_HIP_TRY(hipMemcpy(h, d_cnt, sizeof(h), hipMemcpyDeviceToHost));
+    a->nonzero_words = h[0];
+    a->set_cells = h[1];
+    T_guard.reset();
+    st = sparse_assemble(a.get(), parts);
     if (st != LBL_OK) return st;
     *out = a.release();
     return LBL_OK;
@@ -343,7 +397,7 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
     out->ny = a->ny;
     out->n_words = a->n_words;
     out->row_stride = a->row_stride;
-    out->bits_bytes = a->n_traj * a->row_stride * sizeof(uint64_t);
+    out->bits_bytes = a->T_bits ? a->n_traj * a->row_stride * sizeof(uint64_t) : 0;
     out->int8_bytes = a->T_i8 ? a->n_traj * a->n_words * 64ull : 0;
     out->nonzero_words = a->nonzero_words;
     out->set_cells = a->set_cells;
@@ -380,6 +434,8 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
                 "unknown kernel flag");
     LBL_REQUIRE(kflag != LBL_KERNEL_MFMA_I8 || a->T_i8 != nullptr,
                 "LBL_KERNEL_MFMA_I8 needs an abstraction loaded with LBL_LOAD_KEEP_INT8");
+    LBL_REQUIRE(a->T_bits != nullptr || kflag == LBL_KERNEL_AUTO || kflag == LBL_KERNEL_SPARSE,
+                "the abstraction was loaded with LBL_LOAD_SPARSE_ONLY: only the sparse kernel can label it");
     LBL_REQUIRE(kflag != LBL_KERNEL_SPARSE || a->sp != nullptr,
                 "LBL_KERNEL_SPARSE needs the sparse layout (loaded without LBL_LOAD_NO_SPARSE, fewer than 2^32 rows)");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);

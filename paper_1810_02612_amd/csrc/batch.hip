@@ -193,6 +193,11 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
         by_abs[r.a].push_back(j);
         all_sparse = all_sparse && r.a->sp != nullptr;
     }
+    if (!all_sparse)
+        for (size_t j = 0; j < n_jobs; ++j)
+            LBL_REQUIRE(jobs[j].a->T_bits != nullptr,
+                        "job " + std::to_string(j) + ": loaded sparse only, but another job's abstraction has no "
+                        "sparse layout, so the batch has no common kernel");
     BatchPlan &p = *out;
     p = BatchPlan{};
     p.sparse = all_sparse;

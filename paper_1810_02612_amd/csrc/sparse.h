@@ -88,6 +88,30 @@ constexpr int kBatchTilings = 4;  // 1, 2, 4, 8 tiles per row block
 // Build the tiled layout of a from its bitpacked T (sets a->sp).
 lbl_status build_sparse(lbl_abs *a);
 
+// Entries of a run of whole row blocks, built from that run's bitpacked rows
+// (rows local to each row block, segments ordered row block by row block,
+// then by word).  cnt[rb * n_words + w] is the entry count of segment
+// (rb, w) of the run.  row and val are device arrays of nnz entries.
+struct SparsePart {
+    uint16_t *row = nullptr;
+    uint64_t *val = nullptr;
+    uint64_t nnz = 0;
+    uint32_t n_rb = 0;
+    std::vector<uint32_t> cnt;
+    SparsePart() = default;
+    SparsePart(const SparsePart &) = delete;
+    SparsePart &operator=(const SparsePart &) = delete;
+    SparsePart(SparsePart &&o) noexcept;
+    ~SparsePart();
+};
+// Entries of rows [0, n_rows) of the bitpacked T (row_stride words apart);
+// n_rows is a multiple of kRowBlock except for the abstraction's last run.
+lbl_status sparse_part(const uint64_t *T, uint32_t row_stride, uint64_t n_rows, uint32_t n_words,
+                       SparsePart *out);
+// Concatenate the parts of a's row blocks, in row order, into a's tiled
+// layout and its tilings (sets a->sp); the parts are released.
+lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts);
+
 // Workspace bytes for one frame of n_lane_groups 64-column groups on tiling
 // t (cell masks + per-tile partial labels).
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t = 0);
@@ -121,5 +145,16 @@ std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const st
 // Tiles per row block (at least one each) for `target` tiles in total of
 // about equal cost.
 std::vector<uint32_t> tiles_per_block(const std::vector<double> &cost, uint32_t target);
+// Fixed cost of one tile workgroup in rounds (its start-up latency and the
+// write-back of its partials, about 5 us at the ~28 rounds per microsecond a
+// workgroup retires).
+constexpr double kTileFixedRounds = 128.0;
+// Tiles per row block for a one-frame launch.  Tiles cannot span row blocks,
+// so with fewer row blocks than about twice the CUs one tile per CU leaves
+// some tiles a whole row block; candidate totals of 1 to 4 workgroups per
+// CU are scored by a list schedule (each tile to the CU that frees first,
+// cost per tile plus kTileFixedRounds) and the shortest wins, fewer tiles on
+// near ties.
+std::vector<uint32_t> choose_tiles(const std::vector<double> &cost, uint32_t n_cu);
 
 }  // namespace lbl

@@ -39,6 +39,7 @@
 // nor the split into tiles changes the result.  No global atomics are used.
 #include <algorithm>
 #include <cmath>
+#include <queue>
 
 #include "batch.h"
 #include "profile.h"
@@ -628,6 +629,31 @@ std::vector<uint32_t> tiles_per_block(const std::vector<double> &cost, uint32_t 
     return k;
 }
 
+std::vector<uint32_t> choose_tiles(const std::vector<double> &cost, uint32_t n_cu)
+{
+    std::vector<uint32_t> best_k;
+    double best_end = 0;
+    for (uint32_t m = 2; m <= 8; ++m) {
+        std::vector<uint32_t> k = tiles_per_block(cost, std::max<uint32_t>(1, n_cu * m / 2));
+        // list schedule in row-block order: each tile to the CU that frees first
+        std::priority_queue<double, std::vector<double>, std::greater<double>> cu;
+        for (uint32_t i = 0; i < n_cu; ++i) cu.push(0.0);
+        double end = 0;
+        for (size_t rb = 0; rb < cost.size(); ++rb)
+            for (uint32_t j = 0; j < k[rb]; ++j) {
+                const double t = cu.top() + cost[rb] / k[rb] + kTileFixedRounds;
+                cu.pop();
+                cu.push(t);
+                end = std::max(end, t);
+            }
+        if (best_k.empty() || end < 0.98 * best_end) {  // more tiles only for a clear gain
+            best_k = std::move(k);
+            best_end = end;
+        }
+    }
+    return best_k;
+}
+
 void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
                  const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out)
 {
@@ -764,17 +790,27 @@ static lbl_status upload_tiling(const TilingHost &h, SpTiling *t, size_t *bytes)
     return LBL_OK;
 }
 
-lbl_status build_sparse(lbl_abs *a)
+SparsePart::SparsePart(SparsePart &&o) noexcept
+    : row(o.row), val(o.val), nnz(o.nnz), n_rb(o.n_rb), cnt(std::move(o.cnt))
 {
-    if (a->n_traj >= (1ull << 32)) return LBL_OK;  // row ids are 32-bit: keep only the bitpacked layout
-    const uint32_t W = a->n_words;
+    o.row = nullptr;
+    o.val = nullptr;
+}
+
+SparsePart::~SparsePart()
+{
+    (void)hipFree(row);
+    (void)hipFree(val);
+}
+
+lbl_status sparse_part(const uint64_t *T, uint32_t row_stride, uint64_t n_rows, uint32_t W, SparsePart *out)
+{
     // 1. word-major entries (temporary)
     uint64_t *d_ptr = nullptr, *d_val = nullptr;
     uint32_t *d_row = nullptr;
     LBL_HIP_TRY(hipMalloc(&d_ptr, (size_t)(W + 1) * sizeof(uint64_t)));
     std::unique_ptr<uint64_t, decltype(&hipFree)> g_ptr(d_ptr, &hipFree);
-    hipLaunchKernelGGL(k_wm_count, dim3((W + 7) / 8), dim3(512), 0, nullptr, a->T_bits, a->row_stride, a->n_traj, W,
-                       d_ptr);
+    hipLaunchKernelGGL(k_wm_count, dim3((W + 7) / 8), dim3(512), 0, nullptr, T, row_stride, n_rows, W, d_ptr);
     LBL_HIP_TRY(hipGetLastError());
     std::vector<uint64_t> ptr(W + 1, 0);
     LBL_HIP_TRY(hipMemcpy(ptr.data(), d_ptr, W * sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -785,58 +821,84 @@ lbl_status build_sparse(lbl_abs *a)
         run += n;
     }
     ptr[W] = run;
-    LBL_REQUIRE(run == a->nonzero_words, "sparse layout: word counts disagree with the bitpacked T");
     const uint64_t nnz = run;
     LBL_HIP_TRY(hipMemcpy(d_ptr, ptr.data(), (size_t)(W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
     LBL_HIP_TRY(hipMalloc(&d_row, std::max<uint64_t>(nnz, 1) * sizeof(uint32_t)));
     std::unique_ptr<uint32_t, decltype(&hipFree)> g_row(d_row, &hipFree);
     LBL_HIP_TRY(hipMalloc(&d_val, std::max<uint64_t>(nnz, 1) * sizeof(uint64_t)));
     std::unique_ptr<uint64_t, decltype(&hipFree)> g_val(d_val, &hipFree);
-    hipLaunchKernelGGL(k_wm_fill, dim3((W + 7) / 8), dim3(512), 0, nullptr, a->T_bits, a->row_stride, a->n_traj, W,
-                       d_ptr, d_row, d_val);
+    hipLaunchKernelGGL(k_wm_fill, dim3((W + 7) / 8), dim3(512), 0, nullptr, T, row_stride, n_rows, W, d_ptr, d_row,
+                       d_val);
     LBL_HIP_TRY(hipGetLastError());
 
     // 2. segment counts (every (rb, w), empty ones included) -> offsets (host scan) -> tiled copy
-    std::unique_ptr<SparseLayout> sp(new SparseLayout);
-    sp->n_rb = (uint32_t)((a->n_traj + kRowBlock - 1) / kRowBlock);
-    const uint64_t n_seg = (uint64_t)sp->n_rb * W;
+    out->n_rb = (uint32_t)((n_rows + kRowBlock - 1) / kRowBlock);
+    const uint64_t n_seg = (uint64_t)out->n_rb * W;
     uint32_t *d_cnt = nullptr;
     LBL_HIP_TRY(hipMalloc(&d_cnt, std::max<uint64_t>(n_seg, 1) * sizeof(uint32_t)));
     std::unique_ptr<uint32_t, decltype(&hipFree)> g_cnt(d_cnt, &hipFree);
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, W,
-                       sp->n_rb, d_cnt);
+                       out->n_rb, d_cnt);
     LBL_HIP_TRY(hipGetLastError());
-    std::vector<uint32_t> cnt(n_seg);
-    LBL_HIP_TRY(hipMemcpy(cnt.data(), d_cnt, n_seg * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    out->cnt.assign(n_seg, 0);
+    LBL_HIP_TRY(hipMemcpy(out->cnt.data(), d_cnt, n_seg * sizeof(uint32_t), hipMemcpyDeviceToHost));
     std::vector<uint64_t> seg(n_seg + 1, 0);
-    for (uint64_t s = 0; s < n_seg; ++s) seg[s + 1] = seg[s] + cnt[s];
+    for (uint64_t s = 0; s < n_seg; ++s) seg[s + 1] = seg[s] + out->cnt[s];
     LBL_REQUIRE(seg[n_seg] == nnz, "sparse layout: segment counts disagree with the word counts");
     uint64_t *d_seg = nullptr;
     LBL_HIP_TRY(hipMalloc(&d_seg, (n_seg + 1) * sizeof(uint64_t)));
     std::unique_ptr<uint64_t, decltype(&hipFree)> g_seg(d_seg, &hipFree);
     LBL_HIP_TRY(hipMemcpy(d_seg, seg.data(), (n_seg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+    LBL_HIP_TRY(hipMalloc(&out->row, std::max<uint64_t>(nnz, 1) * sizeof(uint16_t)));
+    LBL_HIP_TRY(hipMalloc(&out->val, std::max<uint64_t>(nnz, 1) * sizeof(uint64_t)));
+    hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, d_val, W,
+                       out->n_rb, d_seg, out->row, out->val);
+    LBL_HIP_TRY(hipGetLastError());
+    LBL_HIP_TRY(hipDeviceSynchronize());
+    out->nnz = nnz;
+    return LBL_OK;
+}
+
+lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
+{
+    const uint32_t W = a->n_words;
+    std::unique_ptr<SparseLayout> sp(new SparseLayout);
+    uint64_t nnz = 0;
+    for (const SparsePart &p : parts) {
+        sp->n_rb += p.n_rb;
+        nnz += p.nnz;
+    }
+    LBL_REQUIRE(sp->n_rb == (a->n_traj + kRowBlock - 1) / kRowBlock, "sparse layout: parts do not cover the rows");
+    LBL_REQUIRE(nnz == a->nonzero_words, "sparse layout: entry count disagrees with the bitpacked T");
     // kEntryPad zeroed entries past the last one: a round's lanes load
     // entries up to 63 past its range without bounds checks
     LBL_HIP_TRY(hipMalloc(&sp->row, (nnz + kEntryPad) * sizeof(uint16_t)));
     LBL_HIP_TRY(hipMalloc(&sp->val, (nnz + kEntryPad) * sizeof(uint64_t)));
     LBL_HIP_TRY(hipMemset(sp->row + nnz, 0, kEntryPad * sizeof(uint16_t)));
     LBL_HIP_TRY(hipMemset(sp->val + nnz, 0, kEntryPad * sizeof(uint64_t)));
-    hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, nullptr, d_ptr, d_row, d_val, W,
-                       sp->n_rb, d_seg, sp->row, sp->val);
-    LBL_HIP_TRY(hipGetLastError());
     sp->nnz = nnz;
 
     // 3. non-empty segments, and the tilings over them
     std::vector<uint64_t> seg_start, rb_seg(sp->n_rb + 1, 0);
     std::vector<uint32_t> seg_word;
-    for (uint32_t rb = 0; rb < sp->n_rb; ++rb) {
-        rb_seg[rb] = seg_word.size();
-        for (uint32_t w = 0; w < W; ++w) {
-            const uint64_t s = (uint64_t)rb * W + w;
-            if (cnt[s] == 0) continue;
-            seg_start.push_back(seg[s]);
-            seg_word.push_back(w);
+    uint64_t at = 0;
+    uint32_t rb = 0;
+    for (SparsePart &p : parts) {
+        if (p.nnz) {
+            LBL_HIP_TRY(hipMemcpy(sp->row + at, p.row, p.nnz * sizeof(uint16_t), hipMemcpyDeviceToDevice));
+            LBL_HIP_TRY(hipMemcpy(sp->val + at, p.val, p.nnz * sizeof(uint64_t), hipMemcpyDeviceToDevice));
         }
+        for (uint32_t r = 0; r < p.n_rb; ++r, ++rb) {
+            rb_seg[rb] = seg_word.size();
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint32_t c = p.cnt[(uint64_t)r * W + w];
+                if (c == 0) continue;
+                seg_start.push_back(at);
+                seg_word.push_back(w);
+                at += c;
+            }
+        }
+        SparsePart done(std::move(p));  // device arrays released here
     }
     rb_seg[sp->n_rb] = seg_word.size();
     seg_start.push_back(nnz);
@@ -849,7 +911,7 @@ lbl_status build_sparse(lbl_abs *a)
     const uint32_t n_cu = (uint32_t)device_cu_count();
     sp->tilings.resize(1 + kBatchTilings);
     for (int i = 0; i <= kBatchTilings; ++i) {
-        std::vector<uint32_t> k = i == 0 ? tiles_per_block(block_costs(seg_start, rb_seg), n_cu)
+        std::vector<uint32_t> k = i == 0 ? choose_tiles(block_costs(seg_start, rb_seg), n_cu)
                                          : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
         TilingHost h;
         make_tiling(seg_start, seg_word, rb_seg, k, &h);
@@ -859,6 +921,15 @@ lbl_status build_sparse(lbl_abs *a)
     LBL_HIP_TRY(hipDeviceSynchronize());
     a->sp = sp.release();
     return LBL_OK;
+}
+
+lbl_status build_sparse(lbl_abs *a)
+{
+    if (a->n_traj >= (1ull << 32)) return LBL_OK;  // row ids are 32-bit: keep only the bitpacked layout
+    std::vector<SparsePart> parts(1);
+    lbl_status st = sparse_part(a->T_bits, a->row_stride, a->n_traj, a->n_words, &parts[0]);
+    if (st != LBL_OK) return st;
+    return sparse_assemble(a, parts);
 }
 
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)

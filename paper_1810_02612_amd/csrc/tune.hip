@@ -73,7 +73,9 @@ Plan default_plan(const lbl_abs *a)
 
 bool plan_usable(const lbl_abs *a, const Plan &p)
 {
-    return !(p.kernel == Kernel::MfmaI8 && !a->T_i8) && !(p.kernel == Kernel::Sparse && !a->sp);
+    if (p.kernel == Kernel::Sparse) return a->sp != nullptr;
+    if (!a->T_bits) return false;  // loaded sparse only
+    return !(p.kernel == Kernel::MfmaI8 && !a->T_i8);
 }
 
 // Synthetic frame: every (cell, proposition) byte is 1 with probability
@@ -135,6 +137,7 @@ lbl_status run_plan(const lbl_abs *a, const Plan &p, const uint8_t *O, uint32_t 
                     hipStream_t s)
 {
     if (p.kernel == Kernel::Sparse) return run_swm(a, O, n_props, Ow, L, s);
+    LBL_REQUIRE(a->T_bits != nullptr, "the abstraction has no bitpacked T (loaded sparse only)");
     uint64_t *ow = static_cast<uint64_t *>(Ow);
     if (p.kernel != Kernel::Bits) {
         lbl_status st = mfma_layout_selftest();
@@ -197,13 +200,14 @@ lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint
     }
     for (int u : {2, 4, 8, 16})
         for (int w : {2, 4, 8}) {
+            if (!a->T_bits) break;  // loaded sparse only
             Plan p;
             p.kernel = Kernel::Bits;
             p.bits.unroll = u;
             p.bits.waves_per_block = w;
             cands.push_back(p);
         }
-    if (mfma_layout_selftest() == LBL_OK) {
+    if (a->T_bits && mfma_layout_selftest() == LBL_OK) {
         for (int m : {1, 2, 4})
             for (int w : {2, 4}) {
                 Plan p;

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "LBL_OK", 1: "LBL_EINVAL", 2: "LBL_ENOMEM", 3: "LBL_EDEVICE",
 LOAD_KEEP_INT8 = 0x1
 LOAD_INPUT_DEVICE = 0x2
 LOAD_NO_SPARSE = 0x4
+LOAD_SPARSE_ONLY = 0x8
 HOST_PTRS = 0x1
 KERNEL_AUTO = 0x00
 KERNEL_BITS = 0x10

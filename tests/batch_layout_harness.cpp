@@ -312,6 +312,43 @@ static void check_tilings()
     check_tiling(start, word, rb_seg, k);
 }
 
+// One-frame tile counts: one tile per CU when the row blocks split finely
+// (the 200k-row headline has 25 blocks), more when a single tile per CU
+// would leave some tiles a whole row block (134 blocks, as 1.1M rows have).
+static void check_choose_tiles()
+{
+    auto total = [](const std::vector<uint32_t> &k) {
+        uint64_t s = 0;
+        for (uint32_t x : k) {
+            CHECK(x >= 1);
+            s += x;
+        }
+        return s;
+    };
+    auto max_tile = [](const std::vector<double> &c, const std::vector<uint32_t> &k) {
+        double m = 0;
+        for (size_t i = 0; i < c.size(); ++i) m = std::max(m, c[i] / k[i]);
+        return m;
+    };
+    const std::vector<double> few(25, 7000.0);
+    CHECK(total(choose_tiles(few, 256)) == 256);
+    const std::vector<double> many(134, 4500.0);
+    const std::vector<uint32_t> k = choose_tiles(many, 256);
+    CHECK(total(k) > 256 && total(k) <= 1024);
+    CHECK(max_tile(many, k) <= 0.5 * 4500.0);
+    // more blocks than candidate tiles: one each
+    const std::vector<double> huge(2000, 100.0);
+    CHECK(total(choose_tiles(huge, 256)) == 2000);
+    // uneven costs stay at least one tile per block, within the candidates
+    std::mt19937 rng(5);
+    for (int trial = 0; trial < 20; ++trial) {
+        std::vector<double> c(1 + rng() % 300);
+        for (double &x : c) x = 1.0 + rng() % 5000;
+        const uint64_t t = total(choose_tiles(c, 256));
+        CHECK(t >= c.size() && t <= std::max<uint64_t>(c.size(), 1024));
+    }
+}
+
 int main()
 {
     // six abstractions at the batched workload's sizes
@@ -365,6 +402,7 @@ int main()
     check_case(abss, jobs, BatchTile{});
     abss[2].sp = keep;
     check_tilings();
+    check_choose_tiles();
     // invalid jobs are rejected without touching anything
     BatchPlan p;
     JobRef bad{&abss[0], nullptr, 8, fake};

@@ -77,6 +77,15 @@ def test_invalid_arguments_are_rejected_without_a_device():
     with pytest.raises(lbl.LblError) as e:
         lbl.load_abstraction(8, 8, rp, ci, flags=0x100)
     assert e.value.status == lbl.EINVAL
+    # sparse only excludes the int8 copy and the no-sparse flag
+    for f in (lbl.LOAD_SPARSE_ONLY | lbl.LOAD_KEEP_INT8, lbl.LOAD_SPARSE_ONLY | lbl.LOAD_NO_SPARSE):
+        with pytest.raises(lbl.LblError) as e:
+            lbl.load_abstraction(8, 8, rp, ci, flags=f)
+        assert e.value.status == lbl.EINVAL and "SPARSE_ONLY" in str(e.value)
+    # the dense loader has no sparse-only mode
+    with pytest.raises(lbl.LblError) as e:
+        lbl.load_abstraction_dense(8, 8, np.zeros((1, 64), np.uint8), flags=lbl.LOAD_SPARSE_ONLY)
+    assert e.value.status == lbl.EINVAL
     with pytest.raises(lbl.LblError):
         lbl.label_frame(None, 1, 8, 1)
     with pytest.raises(lbl.LblError):
