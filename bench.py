@@ -59,6 +59,9 @@ def parse():
     p.add_argument("--serve-seconds", type=float, default=5.0, help="seconds per arrival rate")
     p.add_argument("--serve-rates", default="200,500,1000,2000")
     p.add_argument("--serve-budget-mib", type=int, default=2048)
+    p.add_argument("--no-table1", action="store_true", help="skip the time-augmented workloads of Table 1's sizes")
+    p.add_argument("--table1-sizes", default="154776,295700,568958,836276,1097702")
+    p.add_argument("--table1-steps", type=int, default=20)
     return p.parse_args()
 
 
@@ -296,6 +299,75 @@ def bench_serve(args, lbl, torch, gen, abss):
     return results
 
 
+# Table 1 of the paper (GTX 1080, PCIe transfers included, one proposition
+# per labeling): transitions -> (moving_vehicle ms, not_nominal_lane ms).
+PAPER_TABLE1 = {154776: (3.67, 2.01), 295700: (6.60, 3.25), 568958: (12.77, 5.95), 836276: (18.46, 8.40),
+                1097702: (24.40, 11.02)}
+
+
+def bench_table1(args, lbl, torch, gen, stream):
+    """Time-augmented workloads at Table 1's transition counts (2^21 cells,
+    0.0223% occupancy, the two propositions at about 1% and 90%): each loaded
+    sparse-only, labeled per frame with both propositions on the device, per
+    proposition on the device, and per proposition with host O in and host L
+    out (the paper's timing scope)."""
+    g = gen.SpaceTimeGrid()
+    frames = [gen.spacetime_frame(g, f) for f in range(4)]
+    dens = np.mean([o.mean(axis=0) for o in frames], axis=0)
+    O2 = [torch.from_numpy(o).cuda() for o in frames]
+    O1 = [[torch.from_numpy(np.ascontiguousarray(o[:, p:p + 1])).cuda() for o in frames] for p in range(2)]
+    O1h = [[np.ascontiguousarray(o[:, p:p + 1]) for o in frames] for p in range(2)]
+    flags = lbl.KERNEL_SPARSE
+    rows_out = []
+    for n in [int(x) for x in args.table1_sizes.split(",") if x]:
+        log(f"table1: {n} transitions")
+        t = time.perf_counter()
+        A = gen.spacetime_abstraction(n, g)
+        t_gen = time.perf_counter() - t
+        t = time.perf_counter()
+        h = lbl.load_abstraction(g.nx, g.ny, A.row_ptr, A.col_idx, lbl.LOAD_SPARSE_ONLY)
+        t_load = time.perf_counter() - t
+        del A
+        info = lbl.abstraction_info(h)
+        L2 = torch.empty((n, 2), dtype=torch.uint8, device="cuda")
+        L1 = torch.empty((n, 1), dtype=torch.uint8, device="cuda")
+        for k in range(3):
+            lbl.label_frame(h, O2[k % 4], 2, L2, flags=flags, stream=stream)
+        wall2, _ = timed_steps(lbl, torch, h, O2, 2, L2, flags, args.table1_steps, stream, profile=False)
+        _, prof = timed_steps(lbl, torch, h, O2, 2, L2, flags, args.table1_steps, stream, profile=True)
+        label_ms = prof["label_ms"] / max(1, prof["label_launches"])
+        per_prop, pcie = [], []
+        for p in range(2):
+            w1, _ = timed_steps(lbl, torch, h, O1[p], 1, L1, flags, args.table1_steps, stream, profile=False)
+            per_prop.append(1000 * w1 / args.table1_steps)
+            Lh = np.empty((n, 1), np.uint8)
+            lbl.label_frame(h, O1h[p][0], 1, Lh, flags=flags | lbl.HOST_PTRS)
+            reps = 10
+            t = time.perf_counter()
+            for k in range(reps):
+                lbl.label_frame(h, O1h[p][k % 4], 1, Lh, flags=flags | lbl.HOST_PTRS)
+            pcie.append(1000 * (time.perf_counter() - t) / reps)
+        roof = roofline("sparse", info, n, 2, label_ms)
+        lab = L2.float().mean(dim=0).tolist()
+        lbl.free_abstraction(h)
+        row = {"transitions": n, "entries": info["sparse_entries"], "set_cells": info["set_cells"],
+               "occupancy": info["set_cells"] / (n * g.n_cells), "device_bytes": info["sparse_bytes"],
+               "gen_s": t_gen, "load_s": t_load,
+               "ms_per_frame_both_props": 1000 * wall2 / args.table1_steps,
+               "pairs_per_s": 2 * n * args.table1_steps / wall2, "label_kernel_ms": label_ms,
+               "label_kernel_hbm_frac": roof["frac"],
+               "ms_per_prop_device": {"moving_vehicle": per_prop[0], "not_nominal_lane": per_prop[1]},
+               "ms_per_prop_pcie": {"moving_vehicle": pcie[0], "not_nominal_lane": pcie[1]},
+               "label_true_frac": {"moving_vehicle": lab[0], "not_nominal_lane": lab[1]},
+               "paper_gtx1080_ms_pcie": dict(zip(("moving_vehicle", "not_nominal_lane"), PAPER_TABLE1.get(n, (None, None))))}
+        log("table1", row)
+        rows_out.append(row)
+    return {"grid": "128 x 128 cells of 0.5 m x 128 layers of 0.1 s (2^21 cells)",
+            "prop_density": {"moving_vehicle": float(dens[0]), "not_nominal_lane": float(dens[1])},
+            "load": "LBL_LOAD_SPARSE_ONLY", "kernel": "sparse", "rows": rows_out,
+            "note": "paper figures are context (another GPU, PCIe included), not a baseline"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -447,6 +519,9 @@ def main():
             out["serve"] = bench_serve(args, lbl, torch, gen, abss)
         for _, hb in abss:
             lbl.free_abstraction(hb)
+
+    if not args.no_table1:
+        out["table1"] = bench_table1(args, lbl, torch, gen, stream)
 
     if not args.no_cpu:
         import oracle  # the CPU baseline leg: oracle as it stands, all host threads

@@ -23,6 +23,23 @@ starts with 181002612):
       axis-aligned rectangle (aspect ~ U[0.5, 2]) or a disc with probability
       1/2, centred ~ U(extent), of area -ln(1 - rho) * A / n_s for target
       cell density rho.
+  Time-augmented workload (Sec. 5: the plane and time, 2^21 cells)
+      grid 128 x 128 cells of 0.5 m and 128 layers of 0.1 s, flattened to a
+      128 x 16384 grid (cell id = (layer * 128 + iy) * 128 + ix); a circular
+      road of centre radius 20 m and half width 2 m around the grid centre.
+  T   seed [181002612, 300, 1, 0]; roadmap vertices on the road (angle
+      ~ U[0, 2 pi), radius 20 + U(-0.75, 0.75) m, heading along the road
+      + N(0, 0.05), start layer ~ U{0..116}), 8 transitions per vertex
+      (speed ~ U[4, 12] m/s, curvature 1/radius + U(-0.02, 0.02) 1/m,
+      duration 6 + Binomial(6, 0.455) layers), vertices in order of start layer, then
+      angle; the car footprint at each layer's pose.
+  O   seed [181002612, 300, 2, frame]; proposition 0 (moving vehicle): three
+      other cars circling the road (radius 20 + U(-0.75, 0.75) m, speed
+      ~ U[5, 12] m/s, either direction) over all layers; proposition 1 (not
+      nominal lane): every cell meeting the plane outside the road, in every
+      layer.
+  Bernoulli T and O (Sec. 5.1's random subsets): each cell of each row, and
+      each (cell, proposition), set independently with the given bias.
 """
 from __future__ import annotations
 
@@ -76,6 +93,10 @@ def _load():
     lib.gen_traj_poses.restype = ctypes.c_uint64
     lib.gen_traj_poses.argtypes = [d, d, d, d, d, d, u8, ctypes.c_uint64, ctypes.c_double,
                                    d, ctypes.c_uint64]
+    lib.gen_spacetime.restype = ctypes.c_void_p
+    lib.gen_spacetime.argtypes = [d, d, d, d, d, u32, u32, ctypes.c_uint64, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, u64, u64]
     lib.gen_raster_shapes.restype = None
     lib.gen_raster_shapes.argtypes = [u8, d, d, d, d, u32, ctypes.c_uint64, ctypes.c_uint32,
                                       ctypes.c_double, ctypes.c_uint32, u8]
@@ -327,3 +348,146 @@ def make_batch_abstraction(i: int, cfg: int = 4, scale: float = 1.0,
 def batch_frame_props(cfg: int, abstraction: int, frame: int, lo: int = 4, hi: int = 64) -> int:
     rng = np.random.default_rng([SEED0, cfg, abstraction, 3, frame])
     return int(rng.integers(lo, hi + 1))
+
+
+# ---------------------------------------------------------------- time-augmented workload
+
+@dataclasses.dataclass
+class SpaceTimeGrid:
+    """The plane (n x n cells of side res) times n_tau layers of dt seconds,
+    flattened to an nx x ny grid with ny = n * n_tau."""
+    n: int = 128
+    n_tau: int = 128
+    res: float = 0.5
+    dt: float = 0.1
+
+    @property
+    def nx(self) -> int:
+        return self.n
+
+    @property
+    def ny(self) -> int:
+        return self.n * self.n_tau
+
+    @property
+    def n_cells(self) -> int:
+        return self.n * self.n * self.n_tau
+
+    @property
+    def extent(self) -> float:
+        return self.n * self.res
+
+
+ROAD_RADIUS = 20.0      # m, centre line of the circular road (grid of 64 m)
+ROAD_HALF_WIDTH = 2.0   # m
+TRANSITIONS_PER_VERTEX = 8
+ST_SEED = 300
+
+
+def _road_centre(g: SpaceTimeGrid):
+    return 0.5 * g.extent, 0.5 * g.extent
+
+
+def _spacetime_cells(g: SpaceTimeGrid, x0, y0, th0, k, v, tau0, dur, threads=None):
+    lib = _load()
+    n = len(x0)
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (x0, y0, th0, k, v)]
+    t0 = np.ascontiguousarray(tau0, np.uint32)
+    du = np.ascontiguousarray(dur, np.uint32)
+    counts = np.zeros(n, np.uint64)
+    total = ctypes.c_uint64(0)
+    h = lib.gen_spacetime(*[_ptr(a, ctypes.c_double) for a in arrs], _ptr(t0, ctypes.c_uint32),
+                          _ptr(du, ctypes.c_uint32), n, g.n, g.n_tau, g.res, g.dt, FOOT_LEN, FOOT_WID,
+                          threads or _threads(), _ptr(counts, ctypes.c_uint64), ctypes.byref(total))
+    if not h:
+        raise MemoryError("gen_spacetime failed")
+    try:
+        col = np.empty(int(total.value), np.uint32)
+        lib.gen_raster_fill(h, _ptr(col, ctypes.c_uint32))
+    finally:
+        lib.gen_raster_free(h)
+    row_ptr = np.zeros(n + 1, np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return row_ptr, col
+
+
+def draw_transitions(rng, n_traj: int, g: SpaceTimeGrid) -> dict:
+    """Roadmap transitions on the circular road, ordered by source vertex."""
+    per = TRANSITIONS_PER_VERTEX
+    n_v = -(-n_traj // per)
+    cx, cy = _road_centre(g)
+    phi = rng.uniform(0.0, 2 * math.pi, n_v)
+    r = ROAD_RADIUS + rng.uniform(-0.75, 0.75, n_v)
+    head = phi + 0.5 * math.pi + rng.normal(0.0, 0.05, n_v)
+    tau_v = rng.integers(0, g.n_tau - 12 + 1, n_v)
+    order = np.lexsort((phi, tau_v))
+    phi, r, head, tau_v = phi[order], r[order], head[order], tau_v[order]
+    n = n_v * per
+    v = rng.uniform(4.0, 12.0, n)
+    k = np.repeat(1.0 / r, per) + rng.uniform(-0.02, 0.02, n)
+    dur = 6 + rng.binomial(6, 0.455, n)
+    tr = dict(x0=np.repeat(cx + r * np.cos(phi), per), y0=np.repeat(cy + r * np.sin(phi), per),
+              th0=np.repeat(head, per), k=k, v=v, tau0=np.repeat(tau_v, per), dur=dur)
+    return {key: a[:n_traj] for key, a in tr.items()}
+
+
+def spacetime_abstraction(n_traj: int, g: SpaceTimeGrid | None = None, threads: int | None = None) -> Abstraction:
+    """T of n_traj roadmap transitions in the time-augmented workspace."""
+    g = g or SpaceTimeGrid()
+    rng = np.random.default_rng([SEED0, ST_SEED, 1, 0])
+    tr = draw_transitions(rng, n_traj, g)
+    row_ptr, col = _spacetime_cells(g, tr["x0"], tr["y0"], tr["th0"], tr["k"], tr["v"], tr["tau0"], tr["dur"],
+                                    threads)
+    return Abstraction(grid=g, row_ptr=row_ptr, col_idx=col)
+
+
+def off_road_mask(g: SpaceTimeGrid) -> np.ndarray:
+    """n x n bool: plane cells meeting the region outside the road with
+    positive area (nearest point inside the inner circle, or farthest point
+    outside the outer one)."""
+    cx, cy = _road_centre(g)
+    lo = np.arange(g.n) * g.res
+    X0, Y0 = np.meshgrid(lo, lo)  # [iy, ix]
+    X1, Y1 = X0 + g.res, Y0 + g.res
+    near = np.hypot(np.maximum(np.maximum(X0 - cx, cx - X1), 0.0), np.maximum(np.maximum(Y0 - cy, cy - Y1), 0.0))
+    far = np.hypot(np.maximum(abs(X0 - cx), abs(X1 - cx)), np.maximum(abs(Y0 - cy), abs(Y1 - cy)))
+    return (near < ROAD_RADIUS - ROAD_HALF_WIDTH) | (far > ROAD_RADIUS + ROAD_HALF_WIDTH)
+
+
+def spacetime_frame(g: SpaceTimeGrid | None = None, frame: int = 0, n_agents: int = 3) -> np.ndarray:
+    """O (n_cells x 2 uint8): proposition 0 moving vehicle, 1 not nominal lane."""
+    g = g or SpaceTimeGrid()
+    rng = np.random.default_rng([SEED0, ST_SEED, 2, frame])
+    cx, cy = _road_centre(g)
+    phi = rng.uniform(0.0, 2 * math.pi, n_agents)
+    r = ROAD_RADIUS + rng.uniform(-0.75, 0.75, n_agents)
+    sgn = np.where(rng.uniform(size=n_agents) < 0.5, -1.0, 1.0)
+    v = rng.uniform(5.0, 12.0, n_agents)
+    _, cells = _spacetime_cells(g, cx + r * np.cos(phi), cy + r * np.sin(phi), phi + sgn * 0.5 * math.pi,
+                                sgn / r, v, np.zeros(n_agents), np.full(n_agents, g.n_tau), threads=1)
+    O = np.zeros((g.n_cells, 2), np.uint8)
+    O[cells.astype(np.int64), 0] = 1
+    O[:, 1] = np.tile(off_road_mask(g).reshape(-1), g.n_tau)
+    return O
+
+
+def bernoulli_abstraction(n_traj: int, n_cells: int, p: float, seed: int = 0) -> Abstraction:
+    """Rows with every cell set independently with probability p (sorted ids)."""
+    rng = np.random.default_rng([SEED0, ST_SEED, 3, seed])
+    counts = rng.binomial(n_cells, p, n_traj)
+    rows = []
+    for c in counts:
+        ids = np.unique(rng.integers(0, n_cells, int(c)))
+        while len(ids) < c:  # redraw collisions
+            ids = np.unique(np.concatenate([ids, rng.integers(0, n_cells, int(c) - len(ids))]))
+        rows.append(ids.astype(np.uint32))
+    row_ptr = np.zeros(n_traj + 1, np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.concatenate(rows) if rows else np.zeros(0, np.uint32)
+    return Abstraction(grid=SpaceTimeGrid(), row_ptr=row_ptr, col_idx=col)
+
+
+def bernoulli_frame(n_cells: int, n_props: int, q: float, seed: int = 0) -> np.ndarray:
+    """O with every (cell, proposition) set independently with probability q."""
+    rng = np.random.default_rng([SEED0, ST_SEED, 4, seed])
+    return (rng.uniform(size=(n_cells, n_props)) < q).astype(np.uint8)

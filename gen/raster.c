@@ -42,7 +42,7 @@ typedef struct {
 } chunk_out;
 
 typedef struct {
-    const gen_params *p;
+    const void *p;       /* the generator's parameters */
     chunk_out *out;
 } worker_arg;
 
@@ -214,7 +214,7 @@ static int push_cell(chunk_out *o, uint32_t cell)
 static void *worker(void *va)
 {
     worker_arg *a = (worker_arg *)va;
-    const gen_params *p = a->p;
+    const gen_params *p = (const gen_params *)a->p;
     chunk_out *o = a->out;
     uint32_t wpr = (p->n + 63) / 64;
     uint64_t *bm = (uint64_t *)calloc((uint64_t)wpr * p->n, sizeof(uint64_t));
@@ -252,12 +252,11 @@ static void *worker(void *va)
  * t.  Returns an opaque handle holding the cell ids (fetch with
  * gen_raster_fill, release with gen_raster_free), or NULL on failure.
  */
-void *gen_raster(const double *x0, const double *y0, const double *th0, const double *k0,
-                 const double *k1, const double *len, const uint8_t *kind, uint64_t n_traj,
-                 uint32_t n, double res, double ds, double fl, double fw, int n_threads,
-                 uint64_t *counts, uint64_t *total)
+/* Runs fn over n_chunks row ranges on n_threads threads; counts[t] receives
+ * the number of cells of row t.  Returns the handle or NULL on failure. */
+static gen_handle *run_chunks(void *(*fn)(void *), const void *params, uint64_t n_traj, int n_threads,
+                              uint64_t *counts, uint64_t *total)
 {
-    gen_params p = {x0, y0, th0, k0, k1, len, kind, n_traj, n, res, ds, fl, fw};
     if (n_threads < 1) n_threads = 1;
     int n_chunks = n_threads * 8;
     if ((uint64_t)n_chunks > n_traj) n_chunks = n_traj ? (int)n_traj : 1;
@@ -273,12 +272,12 @@ void *gen_raster(const double *x0, const double *y0, const double *th0, const do
     /* a simple pool: thread k handles chunks k, k + n_threads, ... */
     pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
     worker_arg *args = (worker_arg *)calloc((size_t)n_chunks, sizeof(worker_arg));
-    for (int i = 0; i < n_chunks; ++i) { args[i].p = &p; args[i].out = &h->chunks[i]; }
+    for (int i = 0; i < n_chunks; ++i) { args[i].p = params; args[i].out = &h->chunks[i]; }
     int next = 0;
     while (next < n_chunks) {
         int launched = 0;
         for (int k = 0; k < n_threads && next < n_chunks; ++k, ++next, ++launched)
-            pthread_create(&th[k], NULL, worker, &args[next]);
+            pthread_create(&th[k], NULL, fn, &args[next]);
         for (int k = 0; k < launched; ++k) pthread_join(th[k], NULL);
     }
     free(th);
@@ -298,6 +297,86 @@ void *gen_raster(const double *x0, const double *y0, const double *th0, const do
         return NULL;
     }
     return h;
+}
+
+/*
+ * Rasterize every trajectory.  counts[t] receives the number of cells of row
+ * t.  Returns an opaque handle holding the cell ids (fetch with
+ * gen_raster_fill, release with gen_raster_free), or NULL on failure.
+ */
+void *gen_raster(const double *x0, const double *y0, const double *th0, const double *k0,
+                 const double *k1, const double *len, const uint8_t *kind, uint64_t n_traj,
+                 uint32_t n, double res, double ds, double fl, double fw, int n_threads,
+                 uint64_t *counts, uint64_t *total)
+{
+    gen_params p = {x0, y0, th0, k0, k1, len, kind, n_traj, n, res, ds, fl, fw};
+    return run_chunks(worker, &p, n_traj, n_threads, counts, total);
+}
+
+/*
+ * Space-time swept sets, for the time-augmented workspace (x, y, tau): the
+ * grid has n x n cells of side res in the plane and n_tau time layers of dt
+ * seconds; cell id = (layer * n + iy) * n + ix.  Transition t drives an arc
+ * of curvature k[t] at speed v[t] from (x0, y0, th0); the footprint at the
+ * pose of time j * dt occupies layer tau0[t] + j, j = 0 .. dur[t] - 1 (layers
+ * at or beyond n_tau are dropped), rasterized as in gen_raster.  Cells come
+ * out ascending within a row.
+ */
+typedef struct {
+    const double *x0, *y0, *th0, *k, *v;
+    const uint32_t *tau0, *dur;
+    uint32_t n, n_tau;
+    double res, dt, fl, fw;
+} st_params;
+
+static void *st_worker(void *va)
+{
+    worker_arg *a = (worker_arg *)va;
+    const st_params *p = (const st_params *)a->p;
+    chunk_out *o = a->out;
+    uint32_t wpr = (p->n + 63) / 64;
+    uint64_t *bm = (uint64_t *)calloc((uint64_t)wpr * p->n, sizeof(uint64_t));
+    if (!bm) { o->failed = 1; return NULL; }
+    for (uint64_t t = o->row_lo; t < o->row_hi; ++t) {
+        uint64_t before = o->n_cells;
+        for (uint32_t j = 0; j < p->dur[t]; ++j) {
+            uint64_t layer = (uint64_t)p->tau0[t] + j;
+            if (layer >= p->n_tau) break;
+            double s = p->v[t] * (double)j * p->dt, half = 0.5 * p->k[t] * s;
+            double f = s * sinc(half), mid = p->th0[t] + half;
+            double cx[4], cy[4];
+            footprint(p->x0[t] + f * cos(mid), p->y0[t] + f * sin(mid), p->th0[t] + p->k[t] * s, p->fl, p->fw,
+                      cx, cy);
+            uint32_t bb_lo[2] = {UINT32_MAX, UINT32_MAX}, bb_hi[2] = {0, 0};
+            raster_rect(bm, wpr, p->n, p->res, cx, cy, bb_lo, bb_hi);
+            if (bb_lo[1] == UINT32_MAX) continue;
+            uint32_t w_lo = bb_lo[0] >> 6, w_hi = bb_hi[0] >> 6;
+            for (uint32_t iy = bb_lo[1]; iy <= bb_hi[1]; ++iy) {
+                uint64_t *row = bm + (uint64_t)iy * wpr;
+                for (uint32_t w = w_lo; w <= w_hi; ++w) {
+                    uint64_t val = row[w];
+                    row[w] = 0;
+                    while (val) {
+                        uint32_t b = (uint32_t)__builtin_ctzll(val);
+                        val &= val - 1;
+                        uint64_t cell = (layer * p->n + iy) * p->n + w * 64 + b;
+                        if (push_cell(o, (uint32_t)cell)) { o->failed = 1; free(bm); return NULL; }
+                    }
+                }
+            }
+        }
+        o->counts[t - o->row_lo] = o->n_cells - before;
+    }
+    free(bm);
+    return NULL;
+}
+
+void *gen_spacetime(const double *x0, const double *y0, const double *th0, const double *k, const double *v,
+                    const uint32_t *tau0, const uint32_t *dur, uint64_t n_traj, uint32_t n, uint32_t n_tau,
+                    double res, double dt, double fl, double fw, int n_threads, uint64_t *counts, uint64_t *total)
+{
+    st_params p = {x0, y0, th0, k, v, tau0, dur, n, n_tau, res, dt, fl, fw};
+    return run_chunks(st_worker, &p, n_traj, n_threads, counts, total);
 }
 
 void gen_raster_fill(void *vh, uint32_t *col_idx)

@@ -65,6 +65,9 @@ def _bind(path: str):
     lib.oracle_raster_shapes.restype = ctypes.c_int
     lib.oracle_raster_shapes.argtypes = [u32, u32, d, d, d, d, ctypes.c_uint64, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32, u8]
+    lib.oracle_scan_lengths.restype = ctypes.c_int
+    lib.oracle_scan_lengths.argtypes = [u64, u32, ctypes.c_uint64, u8, ctypes.c_uint32, ctypes.c_uint32,
+                                        u64, ctypes.c_uint64, u64]
     return lib
 
 
@@ -142,3 +145,30 @@ def raster_shapes(kind, prop, cx, cy, a, b, nx: int, ny: int, cell: float, n_pro
     if rc != 0:
         raise ValueError("invalid shape kind or proposition index")
     return O
+
+
+def scan_lengths(row_ptr, col_idx, n_cells: int, O, prop: int, rows=None) -> np.ndarray:
+    """Cells the early-terminating serial scan compares per row (Sec. 5.1):
+    first cell shared by the row and proposition prop, plus one; n_cells if
+    none is shared."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
+    col_idx = np.ascontiguousarray(col_idx, np.uint32)
+    O = np.ascontiguousarray(O, np.uint8)
+    if O.ndim != 2 or O.shape[0] != n_cells or not 0 <= prop < O.shape[1]:
+        raise ValueError("O must be n_cells x n_props and prop one of its columns")
+    n_traj = len(row_ptr) - 1
+    rows = np.arange(n_traj, dtype=np.uint64) if rows is None else np.ascontiguousarray(rows, np.uint64)
+    if len(rows) and int(rows.max()) >= n_traj:
+        raise ValueError("row out of range")
+    if len(col_idx) == 0:
+        col_idx = np.zeros(1, np.uint32)
+    out = np.empty(len(rows), np.uint64)
+    rc = lib.oracle_scan_lengths(_p(row_ptr, ctypes.c_uint64), _p(col_idx, ctypes.c_uint32), n_cells,
+                                 _p(O, ctypes.c_uint8), O.shape[1], prop, _p(rows, ctypes.c_uint64), len(rows),
+                                 _p(out, ctypes.c_uint64))
+    if rc == -1:
+        raise ValueError("column index out of range")
+    if rc == -2:
+        raise ValueError("column ids must ascend within a row")
+    return out

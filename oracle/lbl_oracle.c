@@ -206,3 +206,34 @@ int oracle_raster_shapes(const uint32_t *kind, const uint32_t *prop, const doubl
     }
     return 0;
 }
+
+/*
+ * Early termination (Sec. 5.1, Eq. prob_term): the serial scan behind Eq.
+ * bool_dot examines the cells of row t in ascending id order and may stop at
+ * the first cell that both the trajectory and proposition prop occupy, since
+ * the remaining cells cannot change L[t][prop].  out[i] is the number of cells
+ * that scan compares for row rows[i]: the first shared cell's id plus one, or
+ * n_cells when the row shares no cell with the proposition (L[t][prop] = 0).
+ * Column ids must be ascending within each row.  Returns 0, -1 for a column
+ * id out of range, -2 for ids not ascending.
+ */
+int oracle_scan_lengths(const uint64_t *row_ptr, const uint32_t *col_idx, uint64_t n_cells, const uint8_t *O,
+                        uint32_t n_props, uint32_t prop, const uint64_t *rows, uint64_t n_rows, uint64_t *out)
+{
+    for (uint64_t i = 0; i < n_rows; ++i) {
+        uint64_t t = rows[i];
+        out[i] = n_cells;
+        for (uint64_t k = row_ptr[t]; k < row_ptr[t + 1]; ++k) {
+            if (col_idx[k] >= n_cells) return -1;
+            if (k > row_ptr[t] && col_idx[k] <= col_idx[k - 1]) return -2;
+        }
+        for (uint64_t k = row_ptr[t]; k < row_ptr[t + 1]; ++k) {
+            uint64_t c = col_idx[k];
+            if (O[c * n_props + prop] != 0) {
+                out[i] = c + 1;
+                break;
+            }
+        }
+    }
+    return 0;
+}
