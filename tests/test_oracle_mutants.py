@@ -14,6 +14,7 @@ import pytest
 import oracle
 from tests import test_oracle_pins as pins
 from tests import test_oracle_raster as rpins
+from tests import test_oracle_scan as spins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lbl_oracle.c")
 
@@ -41,6 +42,23 @@ RASTER_MUTANTS = {
     "cells_transposed": ("((uint64_t)iy * nx + ix) * n_props", "((uint64_t)ix * ny + iy) * n_props"),
     "last_shape_dropped": ("for (uint64_t s = 0; s < n_shapes; ++s) {", "for (uint64_t s = 0; s + 1 < n_shapes; ++s) {"),
 }
+
+# mistakes in the early-termination scan counter (oracle_scan_lengths)
+SCAN_MUTANTS = {
+    "scan_off_by_one": ("out[i] = c + 1;", "out[i] = c;"),
+    "scan_counts_entries": ("out[i] = c + 1;", "out[i] = k - row_ptr[t] + 1;"),
+    "scan_ignores_prop": ("if (O[c * n_props + prop] != 0) {", "if (O[c * n_props] != 0) {"),
+    "scan_last_hit": ("                out[i] = c + 1;\n                break;\n", "                out[i] = c + 1;\n"),
+    "scan_miss_is_zero": ("        out[i] = n_cells;\n", "        out[i] = 0;\n"),
+}
+
+
+def run_scan_pins():
+    for args in [(0, 0.05, 0.1), (1, 0.2, 0.02), (2, 0.01, 0.5), (3, 0.3, 0.3)]:
+        spins.test_brute_force(*args)
+    spins.test_special_cases()
+    spins.test_stops_early_iff_labeled()
+    spins.test_bernoulli_scan_length_law(0.9)
 
 
 def run_raster_pins():
@@ -104,6 +122,25 @@ def test_raster_mutant_is_caught(name, tmp_path):
         oracle._lib = saved
 
 
+@pytest.mark.parametrize("name", sorted(SCAN_MUTANTS))
+def test_scan_mutant_is_caught(name, tmp_path):
+    old, new = SCAN_MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-o", str(so), str(path), "-lm", "-lpthread"])
+    saved = oracle._lib
+    oracle._lib = oracle._bind(str(so))
+    try:
+        with pytest.raises((AssertionError, ValueError)):
+            run_scan_pins()
+    finally:
+        oracle._lib = saved
+
+
 def test_unmutated_passes():
     run_pins()
     run_raster_pins()
+    run_scan_pins()
