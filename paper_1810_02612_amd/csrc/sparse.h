@@ -76,6 +76,8 @@ struct SparseLayout {
     uint64_t n_segments = 0;     // non-empty (row block, word) segments
     uint16_t *row = nullptr;     // device [nnz] row within the row block
     uint64_t *val = nullptr;     // device [nnz] word value
+    uint32_t n_used = 0;         // words held by some entry (their tables are packed per frame)
+    uint32_t *used_words = nullptr;  // device [n_used] ascending, or null when every word is used
     // tilings[0]: one frame (about one tile per CU, tiles of equal cost);
     // tilings[1 + i]: 2^i tiles per row block (batches)
     std::vector<SpTiling> tilings;
@@ -149,12 +151,15 @@ std::vector<uint32_t> tiles_per_block(const std::vector<double> &cost, uint32_t 
 // write-back of its partials, about 5 us at the ~28 rounds per microsecond a
 // workgroup retires).
 constexpr double kTileFixedRounds = 128.0;
+// The combine's cost per tile (64 KiB of partials read by the whole chip),
+// in the same units of one workgroup's rounds.
+constexpr double kTileCombineRounds = 0.75;
 // Tiles per row block for a one-frame launch.  Tiles cannot span row blocks,
 // so with fewer row blocks than about twice the CUs one tile per CU leaves
 // some tiles a whole row block; candidate totals of 1 to 4 workgroups per
 // CU are scored by a list schedule (each tile to the CU that frees first,
-// cost per tile plus kTileFixedRounds) and the shortest wins, fewer tiles on
-// near ties.
+// cost per tile plus kTileFixedRounds) plus kTileCombineRounds per tile, and
+// the shortest wins, fewer tiles on near ties.
 std::vector<uint32_t> choose_tiles(const std::vector<double> &cost, uint32_t n_cu);
 
 }  // namespace lbl

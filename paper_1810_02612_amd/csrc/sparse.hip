@@ -19,10 +19,10 @@
 // second segment, and which of its segments' tables must be built first.
 //
 // Per frame:
-//   k_pack_tables  O -> the nibble tables of every word: entry [n][v] is the
-//                  OR of the proposition masks of the cells 4n + b with bit
-//                  b of v set (16 x 16 uint64 per word, one wavefront per
-//                  word).
+//   k_pack_tables  O -> the nibble tables of every word that some entry
+//                  holds: entry [n][v] is the OR of the proposition masks of
+//                  the cells 4n + b with bit b of v set (16 x 16 uint64 per
+//                  word, one wavefront per word).
 //   k_label_tiles  one workgroup per tile.  A wavefront keeps two segments'
 //                  tables in LDS, copying a segment's tables in when a round
 //                  first reaches it (at most one copy per round); every
@@ -156,13 +156,16 @@ k_seg_fill(const uint64_t *__restrict__ wm_ptr, const uint32_t *__restrict__ wm_
 // cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  The
 // word's first cell is read once per wavefront (a scalar load); lane b's
 // cell lies dy rows and dx columns from it, x taking the odd bits of b.
+// Wavefront i packs word words[i], or word i when words is null: only words
+// that some entry of the layout holds need tables.
 __global__ void __launch_bounds__(256)
 k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
-              uint32_t n_words, uint64_t *__restrict__ Tg)
+              const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tg)
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= n_words) return;  // whole wavefronts
+    const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n_items) return;  // whole wavefronts
+    const uint32_t w = words ? words[i] : i;
     const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
     const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
     const uint64_t cell = (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
@@ -646,6 +649,7 @@ std::vector<uint32_t> choose_tiles(const std::vector<double> &cost, uint32_t n_c
                 cu.push(t);
                 end = std::max(end, t);
             }
+        for (uint32_t x : k) end += x * kTileCombineRounds;
         if (best_k.empty() || end < 0.98 * best_end) {  // more tiles only for a clear gain
             best_k = std::move(k);
             best_end = end;
@@ -738,6 +742,7 @@ SparseLayout::~SparseLayout()
 {
     (void)hipFree(row);
     (void)hipFree(val);
+    (void)hipFree(used_words);
     for (SpTiling &t : tilings) {
         (void)hipFree(t.tasks);
         (void)hipFree(t.rounds);
@@ -903,6 +908,20 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
     rb_seg[sp->n_rb] = seg_word.size();
     seg_start.push_back(nnz);
     sp->n_segments = seg_word.size();
+    // the words whose tables a frame needs (all of them: no list)
+    std::vector<uint8_t> used(W, 0);
+    for (uint32_t w : seg_word) used[w] = 1;
+    std::vector<uint32_t> used_list;
+    for (uint32_t w = 0; w < W; ++w)
+        if (used[w]) used_list.push_back(w);
+    sp->n_used = (uint32_t)used_list.size();
+    if (sp->n_used < W && sp->n_used > 0) {
+        LBL_HIP_TRY(hipMalloc(&sp->used_words, used_list.size() * sizeof(uint32_t)));
+        LBL_HIP_TRY(hipMemcpy(sp->used_words, used_list.data(), used_list.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+    } else {
+        sp->n_used = W;
+    }
     // tile workgroups use more than 64 KB of LDS
     LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles<kTileWaves>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
@@ -946,8 +965,8 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     uint64_t *Tg = static_cast<uint64_t *>(ws);
     uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
     void *spn = span_begin(s);
-    hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)a->n_words * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->nx, a->n_words, Tg);
+    hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
+                       n_props, a->d_word_cell, a->nx, sp.used_words, sp.n_used, Tg);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);
