@@ -419,7 +419,7 @@ def draw_transitions(rng, n_traj: int, g: SpaceTimeGrid) -> dict:
     phi = rng.uniform(0.0, 2 * math.pi, n_v)
     r = ROAD_RADIUS + rng.uniform(-0.75, 0.75, n_v)
     head = phi + 0.5 * math.pi + rng.normal(0.0, 0.05, n_v)
-    tau_v = rng.integers(0, g.n_tau - 12 + 1, n_v)
+    tau_v = rng.integers(0, max(1, g.n_tau - 12 + 1), n_v)  # layers past the grid are dropped
     order = np.lexsort((phi, tau_v))
     phi, r, head, tau_v = phi[order], r[order], head[order], tau_v[order]
     n = n_v * per
@@ -431,11 +431,16 @@ def draw_transitions(rng, n_traj: int, g: SpaceTimeGrid) -> dict:
     return {key: a[:n_traj] for key, a in tr.items()}
 
 
-def spacetime_abstraction(n_traj: int, g: SpaceTimeGrid | None = None, threads: int | None = None) -> Abstraction:
-    """T of n_traj roadmap transitions in the time-augmented workspace."""
+def spacetime_abstraction(n_traj: int, g: SpaceTimeGrid | None = None, threads: int | None = None,
+                          shuffle_rows: bool = False) -> Abstraction:
+    """T of n_traj roadmap transitions in the time-augmented workspace, rows
+    in order of source vertex, or in a seeded random order."""
     g = g or SpaceTimeGrid()
     rng = np.random.default_rng([SEED0, ST_SEED, 1, 0])
     tr = draw_transitions(rng, n_traj, g)
+    if shuffle_rows:
+        perm = np.random.default_rng([SEED0, ST_SEED, 5, 0]).permutation(n_traj)
+        tr = {key: a[perm] for key, a in tr.items()}
     row_ptr, col = _spacetime_cells(g, tr["x0"], tr["y0"], tr["th0"], tr["k"], tr["v"], tr["tau0"], tr["dur"],
                                     threads)
     return Abstraction(grid=g, row_ptr=row_ptr, col_idx=col)

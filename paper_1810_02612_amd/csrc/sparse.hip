@@ -283,9 +283,14 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
             st.rec = load_rec(i + kStages);
             st.x = (val_t + e_off)[lane];
             st.r = (row_t + e_off)[lane];
+            // a round that builds no table loads one 32-byte line for the whole
+            // wavefront (still unconditionally): the 2 KiB of its last table
+            // would mostly come from L2, the 16 wavefronts' last tables
+            // filling the CU's L1
             const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)tword * tg_stride);
-            st.tb[0] = src[2 * lane];
-            st.tb[1] = src[2 * lane + 1];
+            const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? 2 * lane : 0u;
+            st.tb[0] = src[tl];
+            st.tb[1] = src[tl + 1];
         };
 
         // the two slot addresses live in vector registers for the whole walk

@@ -68,3 +68,13 @@ def test_bernoulli_inputs():
         assert np.all(np.diff(r.astype(np.int64)) > 0)
     O = gen.bernoulli_frame(1 << 16, 2, 0.3, seed=4)
     assert abs(O.mean() - 0.3) < 0.01
+
+
+def test_shuffled_rows_are_a_permutation_and_short_grids_work():
+    g = gen.SpaceTimeGrid(n=64, n_tau=8, res=1.0)
+    A = gen.spacetime_abstraction(2000, g)
+    B = gen.spacetime_abstraction(2000, g, shuffle_rows=True)
+    rows = lambda X: sorted(tuple(X.col_idx[X.row_ptr[t]:X.row_ptr[t + 1]]) for t in range(2000))
+    assert rows(A) == rows(B)
+    assert not np.array_equal(A.row_ptr, B.row_ptr)
+    assert int(A.col_idx.max()) < g.n_cells
