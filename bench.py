@@ -352,6 +352,18 @@ def bench_table1(args, lbl, torch, gen, stream):
         roof = roofline("sparse", info, n, 2, label_ms)
         lab = L2.float().mean(dim=0).tolist()
         lbl.free_abstraction(h)
+        # the step after labeling: least-cost paths on the product with a
+        # monitor (never off the nominal lane twice in a row), from vertex 0
+        n_v, src, dst, cost = gen.spacetime_roadmap(n, g)
+        dsrc, ddst, dcost = (torch.from_numpy(x.view(np.int32)).cuda() for x in (src, dst, cost))
+        delta = np.array([0, 0, 1, 1, 0, 0, lbl.MONITOR_REJECT, lbl.MONITOR_REJECT], np.uint8)
+        dist = torch.empty(n_v * 2, dtype=torch.int32, device="cuda")
+        pred = torch.empty(n_v * 2, dtype=torch.int32, device="cuda")
+        lbl.product_shortest_paths(n_v, dsrc, ddst, dcost, L2, 2, delta, 0, 0, dist, pred, stream=stream)
+        t = time.perf_counter()
+        sweeps = lbl.product_shortest_paths(n_v, dsrc, ddst, dcost, L2, 2, delta, 0, 0, dist, pred, stream=stream)
+        plan_ms = 1000 * (time.perf_counter() - t)
+        reached = int((dist != -1).sum().item())
         row = {"transitions": n, "entries": info["sparse_entries"], "set_cells": info["set_cells"],
                "occupancy": info["set_cells"] / (n * g.n_cells), "device_bytes": info["sparse_bytes"],
                "gen_s": t_gen, "load_s": t_load,
@@ -361,6 +373,8 @@ def bench_table1(args, lbl, torch, gen, stream):
                "ms_per_prop_device": {"moving_vehicle": per_prop[0], "not_nominal_lane": per_prop[1]},
                "ms_per_prop_pcie": {"moving_vehicle": pcie[0], "not_nominal_lane": pcie[1]},
                "label_true_frac": {"moving_vehicle": lab[0], "not_nominal_lane": lab[1]},
+               "plan": {"vertices": n_v, "monitor_states": 2, "ms": plan_ms, "sweeps": sweeps,
+                        "product_vertices_reached": reached},
                "paper_gtx1080_ms_pcie": dict(zip(("moving_vehicle", "not_nominal_lane"), PAPER_TABLE1.get(n, (None, None))))}
         log("table1", row)
         rows_out.append(row)

@@ -496,3 +496,48 @@ def bernoulli_frame(n_cells: int, n_props: int, q: float, seed: int = 0) -> np.n
     """O with every (cell, proposition) set independently with probability q."""
     rng = np.random.default_rng([SEED0, ST_SEED, 4, seed])
     return (rng.uniform(size=(n_cells, n_props)) < q).astype(np.uint8)
+
+
+def spacetime_roadmap(n_traj: int, g: SpaceTimeGrid | None = None):
+    """The transition system behind spacetime_abstraction's rows: transition
+    t leaves vertex t // 8 and ends at the vertex whose start layer is the
+    first at or after its end layer and whose angle along the road is
+    nearest its end point's (a sink vertex, id n_v, when no vertex starts
+    that late); cost = 1 + its length in millimetres.  Returns (n_vertices,
+    src, dst, cost) as numpy arrays of uint32."""
+    g = g or SpaceTimeGrid()
+    rng = np.random.default_rng([SEED0, ST_SEED, 1, 0])
+    tr = draw_transitions(rng, n_traj, g)
+    per = TRANSITIONS_PER_VERTEX
+    n_v = -(-n_traj // per)
+    cx, cy = _road_centre(g)
+    vx, vy = tr["x0"][::per], tr["y0"][::per]
+    v_layer = tr["tau0"][::per].astype(np.int64)
+    v_phi = np.arctan2(vy - cy, vx - cx)
+    src = (np.arange(n_traj) // per).astype(np.uint32)
+    s = tr["v"] * (tr["dur"] - 1) * g.dt
+    half = 0.5 * tr["k"] * s
+    f = s * np.sinc(half / math.pi)  # sin(half) / half, numpy's sinc is normalised
+    mid = tr["th0"] + half
+    ex, ey = tr["x0"] + f * np.cos(mid), tr["y0"] + f * np.sin(mid)
+    e_phi = np.arctan2(ey - cy, ex - cx)
+    e_layer = tr["tau0"].astype(np.int64) + tr["dur"].astype(np.int64)
+    # vertices are sorted by (layer, angle); the first layer at or after the end
+    layers = np.unique(v_layer)
+    li = np.searchsorted(layers, e_layer)
+    dst = np.full(n_traj, n_v, np.uint32)
+    ok = li < len(layers)
+    two_pi = 2 * math.pi
+    vp = np.mod(v_phi, two_pi)  # ascending within each layer (vertices were sorted by angle)
+    ep = np.mod(e_phi, two_pi)
+    for layer in np.unique(layers[li[ok]]):
+        ts = np.nonzero(ok & (layers[np.minimum(li, len(layers) - 1)] == layer))[0]
+        a = int(np.searchsorted(v_layer, layer, side="left"))
+        b = int(np.searchsorted(v_layer, layer, side="right"))
+        ang = vp[a:b]
+        k = np.searchsorted(ang, ep[ts])
+        cand = np.stack([(k - 1) % (b - a), k % (b - a)])  # neighbours on the circle
+        gap = np.abs(np.angle(np.exp(1j * (ang[cand] - ep[ts][None, :]))))
+        dst[ts] = (a + cand[np.argmin(gap, axis=0), np.arange(len(ts))]).astype(np.uint32)
+    cost = (1 + np.round(1000.0 * s)).astype(np.uint32)
+    return n_v + 1, src, dst, cost

@@ -335,6 +335,57 @@ lbl_status lbl_profile_read(lbl_profile *out);
  */
 lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word, uint32_t *bit);
 
+/*
+ * Minimum-cost paths on the product graph of the transition system and a
+ * runtime monitor (Sec. 3.2): product vertices are pairs (v, q) of a vertex
+ * and a monitor state; a transition e from u to v of cost C(e) joins (u, q)
+ * to (v, q') when the monitor moves from q to q' on the label L(e), and its
+ * product edge costs C(e).  A monitor with no move for a label has met a bad
+ * prefix of the specification (the finite automaton of Sec. 3.2 whose
+ * rejected words are the bad prefixes), so that product edge is absent and
+ * every path found satisfies the specification so far.
+ *
+ *   n_vertices, n_edges  sizes of the transition system; n_vertices > 0,
+ *                        n_vertices * n_states and n_edges * n_states below
+ *                        2^32 - 1.
+ *   src, dst, cost       device arrays of n_edges uint32: the transition's
+ *                        end vertices (< n_vertices) and its cost (>= 1;
+ *                        integer costs make sums exact).
+ *   L, n_props           device array of n_edges x n_props bytes, row e the
+ *                        label of transition e (as written by
+ *                        lbl_label_frame for the rows of T); the monitor reads
+ *                        the label as the bit set sigma = OR over p of
+ *                        (L[e][p] != 0) << p, 1 <= n_props <= 8.
+ *   n_states, delta      the monitor: 1 <= n_states <= 8 states, and a host
+ *                        table of n_states << n_props bytes, delta[(q <<
+ *                        n_props) | sigma] = the next state, or
+ *                        LBL_MONITOR_REJECT where there is no move.
+ *   v0, q0               the start (distance 0).
+ *   dist, pred           device outputs of n_vertices * n_states uint32,
+ *                        index v * n_states + q: the least cost of a path
+ *                        from (v0, q0), and the product edge id e * n_states +
+ *                        q_u of the last step of such a path (the smallest
+ *                        id among the edges that end a least-cost path);
+ *                        0xFFFFFFFF for both when (v, q) is unreachable or
+ *                        only reachable at a cost of 2^32 - 1 or more, and
+ *                        pred = 0xFFFFFFFF at the start.  Following pred
+ *                        from any reached vertex leads back to the start.
+ *   n_sweeps             optional: relaxation sweeps run (the last changes
+ *                        nothing; at most n_vertices * n_states + 1).
+ *
+ * Synchronous: enqueued on hip_stream (0 = the null stream), returns when the
+ * outputs are written.  Uses the stream's workspace (8 bytes per product
+ * vertex).  Errors: LBL_EINVAL for a null pointer, a size or state out of
+ * range, a delta entry that is neither a state nor LBL_MONITOR_REJECT, or an
+ * edge whose vertex is out of range or whose cost is 0 (found on the device;
+ * dist and pred are then unspecified); LBL_ENOMEM; LBL_EDEVICE.
+ */
+#define LBL_MONITOR_REJECT 0xFFu
+lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
+                                      const uint32_t *cost, const uint8_t *L, uint32_t n_props, uint32_t n_states,
+                                      const uint8_t *delta, uint32_t v0, uint32_t q0, uint32_t *dist, uint32_t *pred,
+                                      uint32_t *n_sweeps, void *hip_stream);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *lbl_last_error(void);
 

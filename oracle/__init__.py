@@ -65,6 +65,9 @@ def _bind(path: str):
     lib.oracle_raster_shapes.restype = ctypes.c_int
     lib.oracle_raster_shapes.argtypes = [u32, u32, d, d, d, d, ctypes.c_uint64, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32, u8]
+    lib.oracle_product_paths.restype = ctypes.c_int
+    lib.oracle_product_paths.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u32, u32, u32, u8, ctypes.c_uint32,
+                                         ctypes.c_uint32, u8, ctypes.c_uint32, ctypes.c_uint32, u32, u32]
     lib.oracle_scan_lengths.restype = ctypes.c_int
     lib.oracle_scan_lengths.argtypes = [u64, u32, ctypes.c_uint64, u8, ctypes.c_uint32, ctypes.c_uint32,
                                         u64, ctypes.c_uint64, u64]
@@ -172,3 +175,34 @@ def scan_lengths(row_ptr, col_idx, n_cells: int, O, prop: int, rows=None) -> np.
     if rc == -2:
         raise ValueError("column ids must ascend within a row")
     return out
+
+
+def product_paths(n_vertices: int, src, dst, cost, L, delta, v0: int, q0: int):
+    """(dist, pred) on the product of a transition system and a monitor
+    (Sec. 3.2), each n_vertices * n_states uint32, index v * n_states + q.
+    L: n_edges x n_props labels; delta: n_states << n_props next states
+    (>= n_states: no move)."""
+    lib = _load()
+    src = np.ascontiguousarray(src, np.uint32)
+    dst = np.ascontiguousarray(dst, np.uint32)
+    cost = np.ascontiguousarray(cost, np.uint32)
+    L = np.ascontiguousarray(L, np.uint8)
+    delta = np.ascontiguousarray(delta, np.uint8)
+    n_edges = len(src)
+    n_props = L.shape[1] if L.ndim == 2 else 1
+    n_states = len(delta) >> n_props
+    if n_states < 1 or len(delta) != n_states << n_props:
+        raise ValueError("delta must hold n_states << n_props entries")
+    dist = np.empty(n_vertices * n_states, np.uint32)
+    pred = np.empty(n_vertices * n_states, np.uint32)
+    keep = [a if len(a) else np.zeros(1, a.dtype) for a in (src, dst, cost)]
+    Lk = L if L.size else np.zeros((1, n_props), np.uint8)
+    rc = lib.oracle_product_paths(n_vertices, n_edges, _p(keep[0], ctypes.c_uint32), _p(keep[1], ctypes.c_uint32),
+                                  _p(keep[2], ctypes.c_uint32), _p(Lk, ctypes.c_uint8), n_props, n_states,
+                                  _p(delta, ctypes.c_uint8), v0, q0, _p(dist, ctypes.c_uint32),
+                                  _p(pred, ctypes.c_uint32))
+    if rc == -1:
+        raise ValueError("edge vertex out of range or zero cost")
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return dist, pred

@@ -237,3 +237,122 @@ int oracle_scan_lengths(const uint64_t *row_ptr, const uint32_t *col_idx, uint64
     }
     return 0;
 }
+
+/*
+ * Planning on the product graph (Sec. 3.2): vertices (v, q) of the
+ * transition system and the monitor; transition e from u to v joins (u, q)
+ * to (v, delta[q][sigma_e]) at cost cost[e], where sigma_e is e's label as a
+ * bit set of its n_props propositions and a delta entry >= n_states means the
+ * monitor has no move (a bad prefix: no product edge).  A minimum-cost path
+ * from (v0, q0) is a shortest path in this graph.
+ *
+ * dist[v * Q + q]: the least path cost (Dijkstra with a binary heap; costs
+ * at least 1; a path cost of 2^32 - 1 or more counts as unreachable, value
+ * 0xFFFFFFFF).  pred[v * Q + q]: the smallest product edge id e * Q + q_u over
+ * the product edges into (v, q) with dist[u, q_u] + cost[e] == dist[v, q],
+ * 0xFFFFFFFF at the start and where unreachable.  Returns 0, -1 for a vertex
+ * out of range or a zero cost, -2 if memory runs out.
+ */
+typedef struct { uint64_t d; uint64_t x; } heap_item;
+
+static void heap_push(heap_item *h, uint64_t *n, heap_item it)
+{
+    uint64_t i = (*n)++;
+    while (i > 0) {
+        uint64_t p = (i - 1) / 2;
+        if (h[p].d < it.d || (h[p].d == it.d && h[p].x <= it.x)) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i] = it;
+}
+
+static heap_item heap_pop(heap_item *h, uint64_t *n)
+{
+    heap_item top = h[0], last = h[--(*n)];
+    uint64_t i = 0;
+    for (;;) {
+        uint64_t c = 2 * i + 1;
+        if (c >= *n) break;
+        if (c + 1 < *n && (h[c + 1].d < h[c].d || (h[c + 1].d == h[c].d && h[c + 1].x < h[c].x))) ++c;
+        if (last.d < h[c].d || (last.d == h[c].d && last.x <= h[c].x)) break;
+        h[i] = h[c];
+        i = c;
+    }
+    h[i] = last;
+    return top;
+}
+
+int oracle_product_paths(uint64_t n_vertices, uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
+                         const uint32_t *cost, const uint8_t *L, uint32_t n_props, uint32_t n_states,
+                         const uint8_t *delta, uint32_t v0, uint32_t q0, uint32_t *dist, uint32_t *pred)
+{
+    const uint64_t Q = n_states, n = n_vertices * Q, none = 0xFFFFFFFFull;
+    for (uint64_t e = 0; e < n_edges; ++e)
+        if (src[e] >= n_vertices || dst[e] >= n_vertices || cost[e] == 0) return -1;
+    /* outgoing transitions of each vertex (counting sort by source) */
+    uint64_t *first = (uint64_t *)calloc(n_vertices + 1, sizeof(uint64_t));
+    uint64_t *order = (uint64_t *)malloc((n_edges ? n_edges : 1) * sizeof(uint64_t));
+    uint32_t *sigma = (uint32_t *)malloc((n_edges ? n_edges : 1) * sizeof(uint32_t));
+    uint64_t *d = (uint64_t *)malloc(n * sizeof(uint64_t));
+    uint8_t *done = (uint8_t *)calloc(n, 1);
+    heap_item *heap = (heap_item *)malloc((n_edges * Q + 1) * sizeof(heap_item));
+    if (!first || !order || !sigma || !d || !done || !heap) {
+        free(first); free(order); free(sigma); free(d); free(done); free(heap);
+        return -2;
+    }
+    for (uint64_t e = 0; e < n_edges; ++e) {
+        first[src[e] + 1]++;
+        uint32_t s = 0;
+        for (uint32_t p = 0; p < n_props; ++p) s |= (uint32_t)(L[e * n_props + p] != 0) << p;
+        sigma[e] = s;
+    }
+    for (uint64_t v = 0; v < n_vertices; ++v) first[v + 1] += first[v];
+    {
+        uint64_t *fill = (uint64_t *)malloc((n_vertices + 1) * sizeof(uint64_t));
+        if (!fill) { free(first); free(order); free(sigma); free(d); free(done); free(heap); return -2; }
+        for (uint64_t v = 0; v <= n_vertices; ++v) fill[v] = first[v];
+        for (uint64_t e = 0; e < n_edges; ++e) order[fill[src[e]]++] = e;
+        free(fill);
+    }
+    for (uint64_t i = 0; i < n; ++i) d[i] = none;
+    const uint64_t start = (uint64_t)v0 * Q + q0;
+    d[start] = 0;
+    uint64_t hn = 0;
+    heap_item it0 = {0, start};
+    heap_push(heap, &hn, it0);
+    while (hn > 0) {
+        heap_item it = heap_pop(heap, &hn);
+        if (done[it.x] || it.d != d[it.x]) continue;
+        done[it.x] = 1;
+        const uint64_t u = it.x / Q, q = it.x % Q;
+        for (uint64_t k = first[u]; k < first[u + 1]; ++k) {
+            const uint64_t e = order[k];
+            const uint32_t q2 = delta[(q << n_props) | sigma[e]];
+            if (q2 >= n_states) continue;
+            const uint64_t nd = it.d + cost[e];
+            const uint64_t to = (uint64_t)dst[e] * Q + q2;
+            if (nd >= none || nd >= d[to]) continue;
+            d[to] = nd;
+            heap_item nx = {nd, to};
+            heap_push(heap, &hn, nx);
+        }
+    }
+    /* canonical predecessors: the smallest tight product edge id */
+    for (uint64_t i = 0; i < n; ++i) {
+        dist[i] = (uint32_t)d[i];
+        pred[i] = 0xFFFFFFFFu;
+    }
+    for (uint64_t e = 0; e < n_edges; ++e)
+        for (uint64_t q = 0; q < Q; ++q) {
+            const uint64_t from = (uint64_t)src[e] * Q + q;
+            const uint32_t q2 = delta[(q << n_props) | sigma[e]];
+            if (d[from] == none || q2 >= n_states) continue;
+            const uint64_t to = (uint64_t)dst[e] * Q + q2;
+            if (to == start || d[from] + cost[e] != d[to]) continue;
+            const uint64_t id = e * Q + q;
+            if (id < pred[to]) pred[to] = (uint32_t)id;
+        }
+    free(first); free(order); free(sigma); free(d); free(done); free(heap);
+    return 0;
+}

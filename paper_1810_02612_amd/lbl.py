@@ -38,7 +38,7 @@ EXPORTS = (
     "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_batch", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
     "lbl_serve_start", "lbl_serve_submit", "lbl_serve_wait", "lbl_serve_stats_get", "lbl_serve_stop",
     "lbl_cell_position", "lbl_last_error", "lbl_version", "lbl_profile_enable", "lbl_profile_read",
-    "lbl_raster_frame",
+    "lbl_raster_frame", "lbl_product_shortest_paths",
 )
 
 
@@ -128,6 +128,8 @@ def lib():
         "lbl_profile_enable": [ctypes.c_int],
         "lbl_profile_read": [ctypes.POINTER(Profile)],
         "lbl_raster_frame": [ctypes.POINTER(Grid), ctypes.c_double, vp, u64, u32, vp, vp],
+        "lbl_product_shortest_paths": [u64, u64, vp, vp, vp, vp, u32, u32, vp, u32, u32, vp, vp,
+                                       ctypes.POINTER(ctypes.c_uint32), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -250,6 +252,25 @@ def raster_frame(nx: int, ny: int, cell_m: float, shapes: np.ndarray, n_props: i
     ptr = shapes.ctypes.data if len(shapes) else None
     _check(lib().lbl_raster_frame(ctypes.byref(g), float(cell_m), ptr, len(shapes), n_props, _addr(O),
                                   _stream(stream)))
+
+
+MONITOR_REJECT = 0xFF
+
+
+def product_shortest_paths(n_vertices: int, src, dst, cost, L, n_props: int, delta, v0: int, q0: int, dist, pred,
+                           stream=None) -> int:
+    """Least-cost paths on the product of the transition system (device
+    src/dst/cost/L arrays) and a monitor (host delta table, n_states <<
+    n_props bytes) into device dist/pred arrays (n_vertices * n_states
+    uint32); returns the number of relaxation sweeps."""
+    delta = np.ascontiguousarray(delta, np.uint8)
+    n_states = len(delta) >> n_props
+    sweeps = ctypes.c_uint32(0)
+    n_edges = src.numel() if hasattr(src, "numel") else len(src)
+    _check(lib().lbl_product_shortest_paths(n_vertices, n_edges, _addr(src), _addr(dst), _addr(cost), _addr(L),
+                                            n_props, n_states, delta.ctypes.data, v0, q0, _addr(dist), _addr(pred),
+                                            ctypes.byref(sweeps), _stream(stream)))
+    return sweeps.value
 
 
 def label_batch(jobs, flags: int = 0, stream=None) -> None:
