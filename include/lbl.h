@@ -370,8 +370,11 @@ lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word
  *                        only reachable at a cost of 2^32 - 1 or more, and
  *                        pred = 0xFFFFFFFF at the start.  Following pred
  *                        from any reached vertex leads back to the start.
- *   n_sweeps             optional: relaxation sweeps run (the last changes
- *                        nothing; at most n_vertices * n_states + 1).
+ *   n_sweeps             optional: relaxation sweeps up to and including
+ *                        the first that changed nothing (at most n_vertices *
+ *                        n_states + 1; up to three more run, changing
+ *                        nothing, since sweeps go in groups of four between
+ *                        reads of their flags).
  *
  * Synchronous: enqueued on hip_stream (0 = the null stream), returns when the
  * outputs are written.  Uses the stream's workspace (8 bytes per product

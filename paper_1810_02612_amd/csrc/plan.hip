@@ -12,10 +12,10 @@
 // into the vertex.  Costs are at least 1, so predecessors always have a
 // smaller distance and the predecessor graph is a tree.  A graph with n
 // product vertices needs at most n sweeps (each kernel ends; the host loop
-// is bounded).
+// is bounded).  Sweeps run in groups of kGroup between reads of their flags
+// (a sweep after the fixpoint changes nothing, so the extra ones are
+// harmless), which saves a host synchronization per sweep.
 #include <algorithm>
-#include <cstring>
-#include <vector>
 
 #include "lbl_internal.h"
 
@@ -23,6 +23,7 @@ namespace lbl {
 namespace {
 
 constexpr uint64_t kNone = ~0ull;
+constexpr uint32_t kGroup = 4;  // sweeps per read of the flags
 
 __global__ void __launch_bounds__(256) k_plan_init(uint64_t *__restrict__ best, uint64_t n, uint64_t start)
 {
@@ -116,7 +117,7 @@ extern "C" lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n
     const uint64_t n = n_vertices * n_states;
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     void *ws = nullptr;
-    lbl_status st = workspace(s, up(n * sizeof(uint64_t)) + up(n_delta) + 256, &ws);
+    lbl_status st = workspace(s, up(n * sizeof(uint64_t)) + up(n_delta) + up(2 * kGroup * sizeof(uint32_t)), &ws);
     if (st != LBL_OK) return st;
     uint64_t *best = static_cast<uint64_t *>(ws);
     uint8_t *d_delta = reinterpret_cast<uint8_t *>(ws) + up(n * sizeof(uint64_t));
@@ -125,22 +126,30 @@ extern "C" lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n
     const uint64_t start = (uint64_t)v0 * n_states + q0;
     hipLaunchKernelGGL(k_plan_init, dim3(blocks_for(n)), dim3(256), 0, s, best, n, start);
     LBL_HIP_TRY(hipGetLastError());
-    uint32_t sweeps = 0;
-    for (uint64_t k = 0; k <= n; ++k) {  // Bellman-Ford needs at most n sweeps; the last changes nothing
-        LBL_HIP_TRY(hipMemsetAsync(d_flags, 0, 2 * sizeof(uint32_t), s));
-        hipLaunchKernelGGL(k_plan_relax, dim3(blocks_for(n_edges)), dim3(256), 0, s, src, dst, cost, L, n_props,
-                           n_states, d_delta, n_vertices, n_edges, start, best, d_flags);
-        LBL_HIP_TRY(hipGetLastError());
-        uint32_t h[2] = {0, 0};
+    // Bellman-Ford needs at most n sweeps before one that changes nothing
+    uint64_t sweeps = 0;
+    bool done = false;
+    for (uint64_t run = 0; !done && run <= n; run += kGroup) {
+        LBL_HIP_TRY(hipMemsetAsync(d_flags, 0, 2 * kGroup * sizeof(uint32_t), s));
+        for (uint32_t j = 0; j < kGroup; ++j) {
+            hipLaunchKernelGGL(k_plan_relax, dim3(blocks_for(n_edges)), dim3(256), 0, s, src, dst, cost, L, n_props,
+                               n_states, d_delta, n_vertices, n_edges, start, best, d_flags + 2 * j);
+            LBL_HIP_TRY(hipGetLastError());
+        }
+        uint32_t h[2 * kGroup] = {};
         LBL_HIP_TRY(hipMemcpyAsync(h, d_flags, sizeof(h), hipMemcpyDeviceToHost, s));
         LBL_HIP_TRY(hipStreamSynchronize(s));
-        ++sweeps;
-        LBL_REQUIRE(h[1] == 0, "an edge names a vertex >= n_vertices or has cost 0");
-        if (!h[0]) break;
+        for (uint32_t j = 0; j < kGroup; ++j)
+            LBL_REQUIRE(h[2 * j + 1] == 0, "an edge names a vertex >= n_vertices or has cost 0");
+        for (uint32_t j = 0; j < kGroup && !done; ++j) {
+            ++sweeps;
+            done = h[2 * j] == 0;  // this sweep changed nothing: the fixpoint
+        }
     }
+    LBL_REQUIRE(done, "no fixpoint within the Bellman-Ford bound (cannot happen with costs >= 1)");
     hipLaunchKernelGGL(k_plan_unpack, dim3(blocks_for(n)), dim3(256), 0, s, best, n, dist, pred);
     LBL_HIP_TRY(hipGetLastError());
     LBL_HIP_TRY(hipStreamSynchronize(s));
-    if (n_sweeps) *n_sweeps = sweeps;
+    if (n_sweeps) *n_sweeps = (uint32_t)std::min<uint64_t>(sweeps, 0xFFFFFFFFull);
     return LBL_OK;
 }
