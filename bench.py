@@ -436,6 +436,22 @@ def main():
     log(f"step {ms_per_step:.3f} ms, label kernel {label_ms:.4f} ms, pack {pack_ms:.4f} ms, emit {emit_ms:.4f} ms, "
         f"{roof['achieved']:.0f} {roof['unit']} ({100 * roof['frac']:.1f}%)")
 
+    # per-frame latency over 150 frames (the paper's 150 queries per size):
+    # events on the library's stream around each frame's three kernels
+    lat = []
+    for k in range(150):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lbl.label_frame(h, Os[k % len(Os)], n_props, L, flags=flags, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+    frame_latency = {"frames": len(lat), "mean_ms": float(lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "var_ms2": float(lat.var()),
+                     "note": "one frame at a time, GPU events around its kernels (host waits between frames)"}
+    log("frame latency", frame_latency)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -459,6 +475,7 @@ def main():
                    "plan": plan, "frames": args.frames},
         "roofline": roof,
         "stages_ms": {"pack_O": pack_ms, "label": label_ms, "emit_L": emit_ms},
+        "frame_latency": frame_latency,
     }
 
     if not args.no_pcie:
@@ -553,6 +570,18 @@ def main():
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": frames * pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                                "sample": f"{frames} full frames of the same workload ({dt:.1f} s)"}
+        # the same oracle on one thread, over a bounded sample of rows
+        rows = np.arange(0, a.n_traj, 8, dtype=np.uint64)
+        n1, t0 = 0, time.perf_counter()
+        while True:
+            oracle.label_csr(a.row_ptr, a.col_idx, a.grid.n_cells, Os_host[n1 % len(Os_host)], rows=rows, threads=1)
+            n1 += 1
+            if time.perf_counter() - t0 >= min(3.0, args.cpu_seconds):
+                break
+        dt1 = time.perf_counter() - t0
+        out["cpu_baseline"]["single_thread"] = {
+            "value": n1 * len(rows) * n_props / dt1, "unit": "pairs/s", "cores": 1,
+            "sample": f"{n1} passes over every 8th row of a frame ({dt1:.1f} s)"}
 
     lbl.free_abstraction(h)
     print(json.dumps(out), flush=True)
