@@ -351,11 +351,13 @@ lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word
  *   src, dst, cost       device arrays of n_edges uint32: the transition's
  *                        end vertices (< n_vertices) and its cost (>= 1;
  *                        integer costs make sums exact).
- *   L, n_props           device array of n_edges x n_props bytes, row e the
- *                        label of transition e (as written by
- *                        lbl_label_frame for the rows of T); the monitor reads
- *                        the label as the bit set sigma = OR over p of
- *                        (L[e][p] != 0) << p, 1 <= n_props <= 8.
+ *   L, l_stride, n_props device array of n_edges rows of l_stride bytes,
+ *                        row e the label of transition e (as written by
+ *                        lbl_label_frame for the rows of T, l_stride = that
+ *                        frame's proposition count); the monitor reads the
+ *                        first n_props bytes of a row as the bit set sigma =
+ *                        OR over p of (L[e][p] != 0) << p, 1 <= n_props <= 8
+ *                        and n_props <= l_stride.
  *   n_states, delta      the monitor: 1 <= n_states <= 8 states, and a host
  *                        table of n_states << n_props bytes, delta[(q <<
  *                        n_props) | sigma] = the next state, or
@@ -379,13 +381,14 @@ lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word
  * Synchronous: enqueued on hip_stream (0 = the null stream), returns when the
  * outputs are written.  Uses the stream's workspace (8 bytes per product
  * vertex).  Errors: LBL_EINVAL for a null pointer, a size or state out of
- * range, a delta entry that is neither a state nor LBL_MONITOR_REJECT, or an
+ * range, l_stride < n_props, a delta entry that is neither a state nor LBL_MONITOR_REJECT, or an
  * edge whose vertex is out of range or whose cost is 0 (found on the device;
  * dist and pred are then unspecified); LBL_ENOMEM; LBL_EDEVICE.
  */
 #define LBL_MONITOR_REJECT 0xFFu
 lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
-                                      const uint32_t *cost, const uint8_t *L, uint32_t n_props, uint32_t n_states,
+                                      const uint32_t *cost, const uint8_t *L, uint32_t l_stride, uint32_t n_props,
+                                      uint32_t n_states,
                                       const uint8_t *delta, uint32_t v0, uint32_t q0, uint32_t *dist, uint32_t *pred,
                                       uint32_t *n_sweeps, void *hip_stream);
 

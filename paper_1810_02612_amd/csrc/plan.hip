@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(256) k_plan_init(uint64_t *__restrict__ best, 
 // range or has cost 0.
 __global__ void __launch_bounds__(256)
 k_plan_relax(const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst, const uint32_t *__restrict__ cost,
-             const uint8_t *__restrict__ L, uint32_t n_props, uint32_t n_states, const uint8_t *__restrict__ delta,
+             const uint8_t *__restrict__ L, uint32_t l_stride, uint32_t n_props, uint32_t n_states,
+             const uint8_t *__restrict__ delta,
              uint64_t n_vertices, uint64_t n_edges, uint64_t start, uint64_t *__restrict__ best,
              uint32_t *__restrict__ flags)
 {
@@ -48,7 +49,7 @@ k_plan_relax(const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst,
             continue;
         }
         uint32_t sigma = 0;  // the label as a proposition bit set
-        for (uint32_t p = 0; p < n_props; ++p) sigma |= (L[e * n_props + p] != 0 ? 1u : 0u) << p;
+        for (uint32_t p = 0; p < n_props; ++p) sigma |= (L[e * l_stride + p] != 0 ? 1u : 0u) << p;
         for (uint32_t q = 0; q < n_states; ++q) {
             const uint64_t du = best[(uint64_t)u * n_states + q] >> 32;
             if (du == 0xFFFFFFFFull) continue;  // not reached yet
@@ -93,7 +94,8 @@ using namespace lbl;
 
 extern "C" lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n_edges, const uint32_t *src,
                                                  const uint32_t *dst, const uint32_t *cost, const uint8_t *L,
-                                                 uint32_t n_props, uint32_t n_states, const uint8_t *delta,
+                                                 uint32_t l_stride, uint32_t n_props, uint32_t n_states,
+                                                 const uint8_t *delta,
                                                  uint32_t v0, uint32_t q0, uint32_t *dist, uint32_t *pred,
                                                  uint32_t *n_sweeps, void *hip_stream)
 {
@@ -102,6 +104,7 @@ extern "C" lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n
     LBL_REQUIRE(n_edges == 0 || (src && dst && cost && L), "src, dst, cost or L is null");
     LBL_REQUIRE(delta && dist && pred, "delta, dist or pred is null");
     LBL_REQUIRE(n_props >= 1 && n_props <= 8, "n_props must be in [1, 8]");
+    LBL_REQUIRE(l_stride >= n_props, "l_stride must be at least n_props");
     LBL_REQUIRE(n_states >= 1 && n_states <= 8, "n_states must be in [1, 8]");
     LBL_REQUIRE(v0 < n_vertices && q0 < n_states, "start vertex or state out of range");
     LBL_REQUIRE(n_vertices * n_states < 0xFFFFFFFFull, "too many product vertices (n_vertices * n_states >= 2^32 - 1)");
@@ -132,8 +135,8 @@ extern "C" lbl_status lbl_product_shortest_paths(uint64_t n_vertices, uint64_t n
     for (uint64_t run = 0; !done && run <= n; run += kGroup) {
         LBL_HIP_TRY(hipMemsetAsync(d_flags, 0, 2 * kGroup * sizeof(uint32_t), s));
         for (uint32_t j = 0; j < kGroup; ++j) {
-            hipLaunchKernelGGL(k_plan_relax, dim3(blocks_for(n_edges)), dim3(256), 0, s, src, dst, cost, L, n_props,
-                               n_states, d_delta, n_vertices, n_edges, start, best, d_flags + 2 * j);
+            hipLaunchKernelGGL(k_plan_relax, dim3(blocks_for(n_edges)), dim3(256), 0, s, src, dst, cost, L, l_stride,
+                               n_props, n_states, d_delta, n_vertices, n_edges, start, best, d_flags + 2 * j);
             LBL_HIP_TRY(hipGetLastError());
         }
         uint32_t h[2 * kGroup] = {};

@@ -128,7 +128,7 @@ def lib():
         "lbl_profile_enable": [ctypes.c_int],
         "lbl_profile_read": [ctypes.POINTER(Profile)],
         "lbl_raster_frame": [ctypes.POINTER(Grid), ctypes.c_double, vp, u64, u32, vp, vp],
-        "lbl_product_shortest_paths": [u64, u64, vp, vp, vp, vp, u32, u32, vp, u32, u32, vp, vp,
+        "lbl_product_shortest_paths": [u64, u64, vp, vp, vp, vp, u32, u32, u32, vp, u32, u32, vp, vp,
                                        ctypes.POINTER(ctypes.c_uint32), vp],
     }
     for name, args in sig.items():
@@ -258,17 +258,19 @@ MONITOR_REJECT = 0xFF
 
 
 def product_shortest_paths(n_vertices: int, src, dst, cost, L, n_props: int, delta, v0: int, q0: int, dist, pred,
-                           stream=None) -> int:
+                           stream=None, l_stride: int | None = None) -> int:
     """Least-cost paths on the product of the transition system (device
-    src/dst/cost/L arrays) and a monitor (host delta table, n_states <<
-    n_props bytes) into device dist/pred arrays (n_vertices * n_states
-    uint32); returns the number of relaxation sweeps."""
+    src/dst/cost/L arrays; L rows of l_stride bytes, default n_props, of
+    which the first n_props are read) and a monitor (host delta table,
+    n_states << n_props bytes) into device dist/pred arrays (n_vertices *
+    n_states uint32); returns the number of relaxation sweeps."""
     delta = np.ascontiguousarray(delta, np.uint8)
     n_states = len(delta) >> n_props
     sweeps = ctypes.c_uint32(0)
     n_edges = src.numel() if hasattr(src, "numel") else len(src)
     _check(lib().lbl_product_shortest_paths(n_vertices, n_edges, _addr(src), _addr(dst), _addr(cost), _addr(L),
-                                            n_props, n_states, delta.ctypes.data, v0, q0, _addr(dist), _addr(pred),
+                                            n_props if l_stride is None else l_stride, n_props, n_states,
+                                            delta.ctypes.data, v0, q0, _addr(dist), _addr(pred),
                                             ctypes.byref(sweeps), _stream(stream)))
     return sweeps.value
 

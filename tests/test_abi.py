@@ -145,18 +145,20 @@ def test_planner_rejects_bad_arguments_without_a_device():
     d2 = np.zeros(2, np.uint8)
     fake = 0x1000  # never dereferenced: every call below fails its host checks first
     cases = [
-        lambda: f(0, 1, fake, fake, fake, fake, 1, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # no vertices
-        lambda: f(4, 1, fake, fake, fake, fake, 0, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # n_props 0
-        lambda: f(4, 1, fake, fake, fake, fake, 9, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # n_props 9
-        lambda: f(4, 1, fake, fake, fake, fake, 1, 9, d2.ctypes.data, 0, 0, fake, fake, None, None),   # 9 states
-        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, d2.ctypes.data, 4, 0, fake, fake, None, None),   # v0 out of range
-        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, d2.ctypes.data, 0, 1, fake, fake, None, None),   # q0 out of range
-        lambda: f(4, 1, None, fake, fake, fake, 1, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # null src
-        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, None, 0, 0, fake, fake, None, None),             # null delta
-        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, np.array([0, 3], np.uint8).ctypes.data, 0, 0, fake, fake,
+        lambda: f(0, 1, fake, fake, fake, fake, 1, 1, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # no vertices
+        lambda: f(4, 1, fake, fake, fake, fake, 0, 0, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # n_props 0
+        lambda: f(4, 1, fake, fake, fake, fake, 9, 9, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # n_props 9
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, 9, d2.ctypes.data, 0, 0, fake, fake, None, None),   # 9 states
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, 1, d2.ctypes.data, 4, 0, fake, fake, None, None),   # v0 out of range
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, 1, d2.ctypes.data, 0, 1, fake, fake, None, None),   # q0 out of range
+        lambda: f(4, 1, None, fake, fake, fake, 1, 1, 1, d2.ctypes.data, 0, 0, fake, fake, None, None),   # null src
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, 1, None, 0, 0, fake, fake, None, None),             # null delta
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 1, 1, np.array([0, 3], np.uint8).ctypes.data, 0, 0, fake, fake,
                   None, None),                                                                      # bad next state
-        lambda: f(1 << 31, 1, fake, fake, fake, fake, 1, 2, np.zeros(4, np.uint8).ctypes.data, 0, 0, fake, fake,
+        lambda: f(1 << 31, 1, fake, fake, fake, fake, 1, 1, 2, np.zeros(4, np.uint8).ctypes.data, 0, 0, fake, fake,
                   None, None),                                                                      # 2^32 product vertices
+        lambda: f(4, 1, fake, fake, fake, fake, 1, 2, 1, np.zeros(4, np.uint8).ctypes.data, 0, 0, fake, fake,
+                  None, None),                                                                      # rows narrower than n_props
     ]
     for i, c in enumerate(cases):
         assert c() == lbl.EINVAL, i

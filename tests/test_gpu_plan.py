@@ -79,6 +79,28 @@ def test_random_systems(seed, n_v, n_e, n_props, Q):
     assert 1 <= sweeps <= n_v * Q + 1
 
 
+def test_label_rows_wider_than_the_monitor():
+    """The monitor reads the first n_props bytes of label rows l_stride wide
+    (a frame labeled with more propositions than the monitor watches)."""
+    say("planner: 2 of 37 propositions per label row")
+    rng = np.random.default_rng(9)
+    n_v, n_e, Q = 2000, 20000, 3
+    src = rng.integers(0, n_v, n_e).astype(np.uint32)
+    dst = rng.integers(0, n_v, n_e).astype(np.uint32)
+    cost = rng.integers(1, 21, n_e).astype(np.uint32)
+    Lw = (rng.uniform(size=(n_e, 37)) < 0.3).astype(np.uint8)
+    delta = rng.integers(0, Q, Q << 2).astype(np.uint8)
+    delta[rng.uniform(size=len(delta)) < 0.2] = REJ
+    want_d, want_p = oracle.product_paths(n_v, src, dst, cost, Lw[:, :2], delta, int(src[0]), 0)
+    dist = torch.full((n_v * Q,), 7, dtype=torch.int32, device="cuda")
+    pred = torch.full((n_v * Q,), 7, dtype=torch.int32, device="cuda")
+    lbl.product_shortest_paths(n_v, dev_u32(src), dev_u32(dst), dev_u32(cost), torch.from_numpy(Lw).cuda(), 2, delta,
+                               int(src[0]), 0, dist, pred, l_stride=37)
+    torch.cuda.synchronize()
+    assert_same(dist.cpu().numpy().view(np.uint32), want_d, "dist")
+    assert_same(pred.cpu().numpy().view(np.uint32), want_p, "pred")
+
+
 def roadmap_monitor(avoid_vehicle: bool):
     """Propositions (moving_vehicle, not_nominal_lane) as bits 0 and 1 of the
     label: never leave the nominal lane twice in a row (state 1: the last
