@@ -388,7 +388,7 @@ def bench_table1(args, lbl, torch, gen, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU design shards trajectory rows and is described, not built)"}))
         sys.exit(2)
     import torch
