@@ -78,3 +78,26 @@ def test_shuffled_rows_are_a_permutation_and_short_grids_work():
     assert rows(A) == rows(B)
     assert not np.array_equal(A.row_ptr, B.row_ptr)
     assert int(A.col_idx.max()) < g.n_cells
+
+
+def test_roadmap_edges():
+    """Transition t leaves vertex t // 8 and ends at a vertex that starts no
+    earlier than its end layer (or at the sink), at a cost of at least 1."""
+    g = gen.SpaceTimeGrid()
+    n = 30000
+    n_v, src, dst, cost = gen.spacetime_roadmap(n, g)
+    assert n_v == -(-n // 8) + 1
+    assert np.array_equal(src, np.arange(n) // 8)
+    assert cost.min() >= 1 and dst.max() < n_v
+    rng = np.random.default_rng([gen.SEED0, gen.ST_SEED, 1, 0])
+    tr = gen.draw_transitions(rng, n, g)
+    v_layer = tr["tau0"][::8]
+    real = dst < n_v - 1
+    assert real.mean() > 0.8
+    assert np.all(v_layer[dst[real]] >= tr["tau0"][real] + tr["dur"][real])
+    # the first layer at or after the end: no vertex starts in between
+    layers = np.unique(v_layer)
+    end = tr["tau0"][real] + tr["dur"][real]
+    assert np.array_equal(v_layer[dst[real]], layers[np.searchsorted(layers, end)])
+    # a sink only when no vertex starts that late
+    assert np.all(tr["tau0"][~real] + tr["dur"][~real] > layers.max())
