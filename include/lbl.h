@@ -23,9 +23,10 @@
  *   - Every function returns an lbl_status; nothing throws across the ABI.
  *     On a non-OK status, lbl_last_error() returns a message for the calling
  *     thread, output buffers are unspecified, and no handle is leaked.
- *   - Cells are identified by row-major ids c = iy * nx + ix on the caller's
- *     side.  The library stores cells in its own device order internally; the
- *     result does not depend on it.
+ *   - Cells are identified on the caller's side by ids in the grid's
+ *     cell_order: row-major c = iy * nx + ix by default, or the z-order index
+ *     (LBL_MORTON).  The library stores cells in its own device order
+ *     internally; the result does not depend on it.
  *   - Input bytes follow C truthiness (nonzero = true).  Output bytes are
  *     exactly 0 or 1.
  *   - All sizes are element counts unless stated otherwise.
@@ -59,11 +60,29 @@ typedef struct lbl_server *lbl_server_t; /* a serving loop */
 
 /* Occupancy grid over the rectangular workspace (Sec. 4.1).  nx and ny are
  * cell counts per axis and must be positive multiples of 8; cell_m is the
- * cell side in metres (informational). */
+ * cell side in metres (informational).
+ *
+ * cell_order says how the caller numbers the cells, in every array that is
+ * indexed by cell (CSR column ids and dense columns of T at load, the rows
+ * of O in lbl_label_frame / lbl_label_batch / lbl_serve_submit for an
+ * abstraction loaded with this grid, the rows written by lbl_raster_frame,
+ * the id given to lbl_cell_position):
+ *   LBL_ROW_MAJOR  c = iy * nx + ix (the default);
+ *   LBL_MORTON     c = the z-order index of cell (ix, iy) (Sec. 4.1,
+ *                  Alg. zcurve, read as bit interleaving with x as the more
+ *                  significant bit of each pair: c = sum over bits b of
+ *                  bit b of ix * 2^(2b+1) + bit b of iy * 2^(2b)).  Needs a
+ *                  square grid whose side is a power of two (nx == ny ==
+ *                  2^k, k >= 3), so that the ids are exactly 0 .. nx*ny - 1.
+ * Labels do not depend on the order: the same T and O numbered either way
+ * give the same L. */
+#define LBL_ROW_MAJOR 0u
+#define LBL_MORTON 1u
+
 typedef struct {
     uint32_t nx, ny;
     float cell_m;
-    uint32_t reserved; /* must be 0 */
+    uint32_t cell_order; /* LBL_ROW_MAJOR or LBL_MORTON */
 } lbl_grid;
 
 /* ---- flags for lbl_load_abstraction* ---------------------------------- */
@@ -94,8 +113,9 @@ typedef struct {
  * Load T given in compressed sparse row form (Sec. 4.3, Eq. csr_demo):
  * row_ptr[t] is the number of true entries in rows 0..t-1 (n_traj + 1
  * values, row_ptr[0] == 0, non-decreasing) and col_idx[row_ptr[t] ..
- * row_ptr[t+1]) are the row-major cell ids of row t's true entries.  Column
- * ids may be unsorted or repeated within a row (OR is idempotent).
+ * row_ptr[t+1]) are the cell ids (in the grid's cell_order) of row t's true
+ * entries.  Column ids may be unsorted or repeated within a row (OR is
+ * idempotent).
  *
  * The arrays are host pointers unless LBL_LOAD_INPUT_DEVICE is set.  They are
  * copied; the caller may free them when the call returns.  The returned
@@ -108,7 +128,8 @@ typedef struct {
  * gigabyte.  Labels are identical to those of a full load.
  *
  * Errors: LBL_EINVAL for a null pointer, n_traj == 0, nx or ny not a positive
- * multiple of 8, reserved != 0, row_ptr[0] != 0 or decreasing, a column id
+ * multiple of 8, an unknown cell_order or LBL_MORTON on a grid that is not a
+ * square of power-of-two side, row_ptr[0] != 0 or decreasing, a column id
  * >= nx * ny, an unknown or contradictory flag, or LBL_LOAD_SPARSE_ONLY with
  * 2^32 rows or more; LBL_ENOMEM if device memory runs out; LBL_EDEVICE on a
  * HIP error.
@@ -117,8 +138,9 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
                                 const uint32_t *col_idx, uint32_t flags, lbl_abs_t *out);
 
 /*
- * Load T given dense: n_traj x (nx * ny) bytes, row-major, cell ids
- * row-major (nonzero = cell swept).  Otherwise as lbl_load_abstraction.
+ * Load T given dense: n_traj x (nx * ny) bytes, row-major (row t holds its
+ * cells in the grid's cell_order; nonzero = cell swept).  Otherwise as
+ * lbl_load_abstraction.
  */
 lbl_status lbl_load_abstraction_dense(const lbl_grid *grid, uint64_t n_traj, const uint8_t *T,
                                       uint32_t flags, lbl_abs_t *out);
@@ -150,13 +172,16 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);
 
 /*
  * Label one frame (Eq. approx).
- *   O : n_cells x n_props bytes, cell-major (O[c * n_props + p]), c row-major;
+ *   O : n_cells x n_props bytes, cell-major (O[c * n_props + p]), c numbered
+ *       in the cell_order of the grid the abstraction was loaded with;
  *   L : n_traj x n_props bytes, row-major (L[t * n_props + p]), written 0/1.
  *   n_props in [1, 64].
  * With LBL_HOST_PTRS, O and L are host memory and the call returns after L
  * is written (the transfers are part of the call).  Otherwise both are
  * device pointers and the call is asynchronous on hip_stream.  Distinct
- * streams may label the same abstraction concurrently.
+ * streams may label the same abstraction concurrently.  Calls on one stream
+ * from several host threads at once are not supported: they share that
+ * stream's workspace.
  *
  * The first call on a stream (or one needing a larger workspace) allocates
  * and synchronizes that stream; later calls do not.
@@ -213,7 +238,7 @@ lbl_status lbl_label_batch(const lbl_job *jobs, size_t n_jobs, uint32_t flags, v
  * Cell (ix, iy) is the square [ix * cell_m, ix * cell_m + cell_m] x
  * [iy * cell_m, iy * cell_m + cell_m], computed in double precision, and O is
  * written as lbl_label_frame reads it: n_cells x n_props bytes, cells
- * row-major (iy * nx + ix), exactly 0 or 1.  cell_m is given here in double
+ * numbered in the grid's cell_order, exactly 0 or 1.  cell_m is given here in double
  * precision (the grid's float cell_m is informational).
  *
  * shapes: host array of n_shapes entries, read during the call (the caller
@@ -270,7 +295,10 @@ lbl_status lbl_tune_describe(lbl_abs_t a, uint32_t n_props, char *buf, size_t bu
  * internal per-request buffers) frees up, grouped per abstraction into
  * batches of at most max_batch_frames, and a batch is launched while earlier
  * ones are still running.  The library does not copy O or L: both must stay
- * valid until lbl_serve_wait returns LBL_OK for the ticket.
+ * valid until lbl_serve_wait returns LBL_OK for the ticket.  The server's
+ * streams are not ordered after the caller's: O (and any earlier write to L)
+ * must be complete on the device when lbl_serve_submit is called, e.g. by
+ * synchronizing the stream that produced them.
  *
  * lbl_serve_wait blocks until the ticket completes (LBL_OK), timeout_us
  * elapses (LBL_ETIMEDOUT; negative = wait forever), or the request failed
@@ -331,7 +359,9 @@ lbl_status lbl_profile_read(lbl_profile *out);
  * among the grid's tiles when the tile grid is not a power-of-two square) and
  * bits follow the z-order of the cells inside the tile, x as the more
  * significant bit of each pair.  For a 2^k x 2^k grid, word * 64 + bit is the
- * cell's z-order index.  Host-only; needs no device.
+ * cell's z-order index (so with LBL_MORTON ids, word = cell / 64 and bit =
+ * cell % 64).  cell is numbered in the grid's cell_order.  Host-only; needs
+ * no device.
  */
 lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word, uint32_t *bit);
 

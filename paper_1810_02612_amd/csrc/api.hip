@@ -29,10 +29,11 @@ uint32_t morton2(uint32_t x, uint32_t y)
     return (spread(x) << 1) | spread(y);
 }
 
-void CellOrder::build(uint32_t nx_, uint32_t ny_)
+void CellOrder::build(uint32_t nx_, uint32_t ny_, bool morton_)
 {
     nx = nx_;
     ny = ny_;
+    morton = morton_;
     ntx = nx / 8;
     nty = ny / 8;
     n_words = ntx * nty;
@@ -49,7 +50,9 @@ void CellOrder::build(uint32_t nx_, uint32_t ny_)
             for (uint32_t dy = 0; dy < 8; ++dy)
                 for (uint32_t dx = 0; dx < 8; ++dx) {
                     const uint32_t b = morton2(dx, dy);
-                    word_cell[(size_t)w * 64 + b] = (ty * 8 + dy) * nx + (tx * 8 + dx);
+                    // z-order ids: the device position is the caller's id
+                    word_cell[(size_t)w * 64 + b] =
+                        morton ? morton2(tx * 8 + dx, ty * 8 + dy) : (ty * 8 + dy) * nx + (tx * 8 + dx);
                 }
         }
 }
@@ -91,13 +94,16 @@ lbl_status workspace(hipStream_t s, size_t bytes, void **out)
     return LBL_OK;
 }
 
-static lbl_status check_grid(const lbl_grid *g)
+lbl_status check_grid(const lbl_grid *g)
 {
     LBL_REQUIRE(g != nullptr, "grid is null");
-    LBL_REQUIRE(g->reserved == 0, "grid.reserved must be 0");
+    LBL_REQUIRE(g->cell_order == LBL_ROW_MAJOR || g->cell_order == LBL_MORTON,
+                "grid.cell_order must be LBL_ROW_MAJOR or LBL_MORTON");
     LBL_REQUIRE(g->nx > 0 && g->ny > 0 && g->nx % 8 == 0 && g->ny % 8 == 0,
                 "grid nx and ny must be positive multiples of 8");
     LBL_REQUIRE((uint64_t)g->nx * g->ny <= (1ull << 31), "grid has more than 2^31 cells");
+    LBL_REQUIRE(g->cell_order != LBL_MORTON || (g->nx == g->ny && (g->nx & (g->nx - 1)) == 0),
+                "LBL_MORTON cell ids need a square grid whose side is a power of two");
     return LBL_OK;
 }
 
@@ -111,7 +117,7 @@ static lbl_status abs_alloc(const lbl_grid *g, uint64_t n_traj, std::unique_ptr<
     a->cell_m = g->cell_m;
     a->n_traj = n_traj;
     a->n_cells = g->nx * g->ny;
-    a->order.build(g->nx, g->ny);
+    a->order.build(g->nx, g->ny, g->cell_order == LBL_MORTON);
     a->n_words = a->order.n_words;
     a->row_stride = (a->n_words + 1) & ~1u;
     LBL_HIP_TRY(hipMalloc(&a->d_tile_word, a->order.tile_word.size() * sizeof(uint32_t)));
@@ -193,6 +199,11 @@ lbl_status lbl_cell_position(const lbl_grid *grid, uint32_t cell, uint32_t *word
     if (st != LBL_OK) return st;
     LBL_REQUIRE(word && bit, "null output pointer");
     LBL_REQUIRE((uint64_t)cell < (uint64_t)grid->nx * grid->ny, "cell id out of range");
+    if (grid->cell_order == LBL_MORTON) {  // the z-order index is the device position
+        *word = cell >> 6;
+        *bit = cell & 63u;
+        return LBL_OK;
+    }
     // rank of the tile among the grid's tiles in z-order
     const uint32_t ix = cell % grid->nx, iy = cell / grid->nx;
     const uint32_t ntx = grid->nx / 8, nty = grid->ny / 8;
@@ -271,7 +282,8 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
     auto pack_rows = [&](uint64_t *T, uint64_t first, uint64_t t_begin, uint64_t t_end) -> lbl_status {
         if (dev_in) {
             LBL_HIP_TRY(launch_pack_csr(T, a->row_stride, row_ptr + t_begin, t_begin - first, t_end - t_begin,
-                                        col_idx, 0, a->d_tile_word, a->nx, a->n_cells, d_bad, nullptr));
+                                        col_idx, 0, a->d_tile_word, a->nx, a->n_cells, a->order.morton, d_bad,
+                                        nullptr));
             LBL_HIP_TRY(hipDeviceSynchronize());
             return LBL_OK;
         }
@@ -282,7 +294,7 @@ lbl_status lbl_load_abstraction(const lbl_grid *grid, uint64_t n_traj, const uin
             LBL_HIP_TRY(hipMemcpy(d_rp, rp + t0, (t1 - t0 + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
             if (nc) LBL_HIP_TRY(hipMemcpy(d_ci, col_idx + rp[t0], nc * sizeof(uint32_t), hipMemcpyHostToDevice));
             LBL_HIP_TRY(launch_pack_csr(T, a->row_stride, d_rp, t0 - first, t1 - t0, d_ci, rp[t0], a->d_tile_word,
-                                        a->nx, a->n_cells, d_bad, nullptr));
+                                        a->nx, a->n_cells, a->order.morton, d_bad, nullptr));
             LBL_HIP_TRY(hipDeviceSynchronize());
             t0 = t1;
         }

@@ -39,12 +39,20 @@ void clear_error();
 // Device cell order: 8x8 tiles, one uint64 word per tile, words ranked by the
 // tiles' z-order, bits by the cells' z-order inside the tile (x is the more
 // significant bit of each pair).
+// word_cell maps a device position to the caller's cell id: the row-major id,
+// or, for callers numbering cells in z-order (LBL_MORTON, square grids of
+// power-of-two side), the position itself (word * 64 + bit is the z-order
+// index there).
 struct CellOrder {
     uint32_t nx = 0, ny = 0, ntx = 0, nty = 0, n_words = 0;
+    bool morton = false;
     std::vector<uint32_t> tile_word;  // [nty * ntx] -> word index
-    std::vector<uint32_t> word_cell;  // [n_words * 64] -> row-major cell id
-    void build(uint32_t nx, uint32_t ny);
+    std::vector<uint32_t> word_cell;  // [n_words * 64] -> caller's cell id
+    void build(uint32_t nx, uint32_t ny, bool morton = false);
 };
+
+// Validates a grid (sizes, cell_order) for any entry point.
+lbl_status check_grid(const lbl_grid *g);
 
 uint32_t morton2(uint32_t x, uint32_t y);  // x bits at odd positions
 
@@ -99,10 +107,11 @@ hipError_t launch_label_bits(const lbl_abs *a, const uint64_t *Ow, uint32_t n_pr
                              const BitsTile &tile, hipStream_t s);
 
 // T packers used at load time.
+// Column ids are row-major unless morton (then word = id / 64, bit = id % 64).
 hipError_t launch_pack_csr(uint64_t *T, uint32_t row_stride, const uint64_t *row_ptr,
                            uint64_t row_base, uint64_t n_rows, const uint32_t *col_idx,
                            uint64_t col_base, const uint32_t *tile_word, uint32_t nx,
-                           uint32_t n_cells, uint32_t *bad, hipStream_t s);
+                           uint32_t n_cells, bool morton, uint32_t *bad, hipStream_t s);
 hipError_t launch_pack_dense(uint64_t *T, uint32_t row_stride, const uint8_t *Td, uint64_t n_rows,
                              uint32_t n_cells, const uint32_t *word_cell, uint32_t n_words,
                              hipStream_t s);

@@ -13,11 +13,12 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)
 }
 
 // One workgroup per row: OR every listed cell's bit into the zeroed row.
-// A column id outside the grid sets *bad and is skipped.
+// A column id outside the grid sets *bad and is skipped.  Ids are row-major,
+// or z-order indices when morton (the device position itself).
 __global__ void __launch_bounds__(256)
 k_pack_csr(uint64_t *__restrict__ T, uint32_t row_stride, const uint64_t *__restrict__ row_ptr,
            uint64_t row_base, uint64_t n_rows, const uint32_t *__restrict__ col_idx, uint64_t col_base,
-           const uint32_t *__restrict__ tile_word, uint32_t nx, uint32_t n_cells, uint32_t *bad)
+           const uint32_t *__restrict__ tile_word, uint32_t nx, uint32_t n_cells, uint32_t morton, uint32_t *bad)
 {
     const uint64_t r = blockIdx.x;
     if (r >= n_rows) return;
@@ -30,9 +31,15 @@ k_pack_csr(uint64_t *__restrict__ T, uint32_t row_stride, const uint64_t *__rest
             atomicOr(bad, 1u);
             continue;
         }
-        const uint32_t ix = c % nx, iy = c / nx;
-        const uint32_t w = tile_word[(iy >> 3) * ntx + (ix >> 3)];
-        const uint32_t b = (spread3(ix & 7u) << 1) | spread3(iy & 7u);
+        uint32_t w, b;
+        if (morton) {
+            w = c >> 6;
+            b = c & 63u;
+        } else {
+            const uint32_t ix = c % nx, iy = c / nx;
+            w = tile_word[(iy >> 3) * ntx + (ix >> 3)];
+            b = (spread3(ix & 7u) << 1) | spread3(iy & 7u);
+        }
         atomicOr(reinterpret_cast<unsigned long long *>(Tr + w), 1ull << b);
     }
 }
@@ -137,12 +144,12 @@ static unsigned grid_for(uint64_t items, unsigned per_block, unsigned cap = 1u <
 
 hipError_t launch_pack_csr(uint64_t *T, uint32_t row_stride, const uint64_t *row_ptr, uint64_t row_base,
                            uint64_t n_rows, const uint32_t *col_idx, uint64_t col_base,
-                           const uint32_t *tile_word, uint32_t nx, uint32_t n_cells, uint32_t *bad,
-                           hipStream_t s)
+                           const uint32_t *tile_word, uint32_t nx, uint32_t n_cells, bool morton,
+                           uint32_t *bad, hipStream_t s)
 {
     if (n_rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_csr, dim3((unsigned)n_rows), dim3(256), 0, s, T, row_stride, row_ptr,
-                       row_base, n_rows, col_idx, col_base, tile_word, nx, n_cells, bad);
+                       row_base, n_rows, col_idx, col_base, tile_word, nx, n_cells, (uint32_t)morton, bad);
     return hipGetLastError();
 }
 

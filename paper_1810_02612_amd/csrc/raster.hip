@@ -30,6 +30,15 @@ unsigned zero_blocks(uint64_t n_bytes)
     return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 1), 4096);
 }
 
+// z-order index of cell (ix, iy): bits of ix at the odd positions, of iy at
+// the even ones (x the more significant bit of each pair).
+__device__ __forceinline__ uint32_t z_index(uint32_t ix, uint32_t iy)
+{
+    uint32_t z = 0;
+    for (int b = 0; b < 16; ++b) z |= ((ix >> b) & 1u) << (2 * b + 1) | ((iy >> b) & 1u) << (2 * b);
+    return z;
+}
+
 __global__ void __launch_bounds__(256) k_zero_bytes(uint8_t *__restrict__ O, uint64_t n)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -45,7 +54,7 @@ __global__ void __launch_bounds__(256) k_zero_bytes(uint8_t *__restrict__ O, uin
 
 __global__ void __launch_bounds__(256)
 k_raster_shapes(const lbl_shape *__restrict__ shapes, uint32_t nx, uint32_t ny, double cell, uint32_t n_props,
-                uint8_t *__restrict__ O)
+                uint32_t morton, uint8_t *__restrict__ O)
 {
 #pragma clang fp contract(off)
     const lbl_shape sh = shapes[blockIdx.x];
@@ -74,7 +83,7 @@ k_raster_shapes(const lbl_shape *__restrict__ shapes, uint32_t nx, uint32_t ny, 
             const double ex = sh.cx - qx, ey = sh.cy - qy;
             hit = ex * ex + ey * ey < sh.a * sh.a;
         }
-        if (hit) O[((uint64_t)iy * nx + ix) * n_props + sh.prop] = 1;
+        if (hit) O[(morton ? (uint64_t)z_index(ix, iy) : (uint64_t)iy * nx + ix) * n_props + sh.prop] = 1;
     }
 }
 
@@ -89,10 +98,10 @@ lbl_status lbl_raster_frame(const lbl_grid *g, double cell_m, const lbl_shape *s
     clear_error();
     LBL_REQUIRE(g != nullptr && O != nullptr, "grid or O is null");
     LBL_REQUIRE(n_shapes == 0 || shapes != nullptr, "shapes is null");
-    LBL_REQUIRE(g->reserved == 0, "grid.reserved must be 0");
-    LBL_REQUIRE(g->nx > 0 && g->ny > 0 && g->nx % 8 == 0 && g->ny % 8 == 0,
-                "grid nx and ny must be positive multiples of 8");
-    LBL_REQUIRE((uint64_t)g->nx * g->ny <= (1ull << 31), "grid has more than 2^31 cells");
+    {
+        const lbl_status gst = check_grid(g);
+        if (gst != LBL_OK) return gst;
+    }
     LBL_REQUIRE(n_props >= 1 && n_props <= 64, "n_props must be in [1, 64]");
     LBL_REQUIRE(std::isfinite(cell_m) && cell_m > 0.0, "cell_m must be finite and positive");
     LBL_REQUIRE(n_shapes < (1ull << 31), "too many shapes");
@@ -115,7 +124,7 @@ lbl_status lbl_raster_frame(const lbl_grid *g, double cell_m, const lbl_shape *s
     lbl_shape *d_shapes = static_cast<lbl_shape *>(ws);
     LBL_HIP_TRY(hipMemcpyAsync(d_shapes, shapes, n_shapes * sizeof(lbl_shape), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_raster_shapes, dim3((unsigned)n_shapes, kRasterSlices), dim3(256), 0, st, d_shapes, g->nx,
-                       g->ny, cell_m, n_props, O);
+                       g->ny, cell_m, n_props, (uint32_t)(g->cell_order == LBL_MORTON), O);
     LBL_HIP_TRY(hipGetLastError());
     return LBL_OK;
 }

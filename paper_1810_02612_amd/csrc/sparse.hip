@@ -153,14 +153,15 @@ k_seg_fill(const uint64_t *__restrict__ wm_ptr, const uint32_t *__restrict__ wm_
 
 
 // One wavefront per word, one lane per cell: the mask of the propositions
-// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  The
-// word's first cell is read once per wavefront (a scalar load); lane b's
-// cell lies dy rows and dx columns from it, x taking the odd bits of b.
-// Wavefront i packs word words[i], or word i when words is null: only words
-// that some entry of the layout holds need tables.
+// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  With
+// row-major cell ids the word's first cell is read once per wavefront (a
+// scalar load) and lane b's cell lies dy rows and dx columns from it, x
+// taking the odd bits of b; with z-order ids (morton) lane b's cell is
+// w * 64 + b.  Wavefront i packs word words[i], or word i when words is null:
+// only words that some entry of the layout holds need tables.
 __global__ void __launch_bounds__(256)
 k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
-              const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tg)
+              uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tg)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -168,7 +169,8 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
     const uint32_t w = words ? words[i] : i;
     const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
     const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
-    const uint64_t cell = (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
+    const uint64_t cell = morton ? (uint64_t)w * 64 + lane
+                                 : (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
     write_tables(byte_mask(O + cell * n_props, n_props), Tg + (uint64_t)w * 256, lane);
 }
 
@@ -971,7 +973,7 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
     void *spn = span_begin(s);
     hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->nx, sp.used_words, sp.n_used, Tg);
+                       n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);

@@ -21,6 +21,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ETIMEDOUT, ECLOSED = range(7)
 STATUS_NAMES = {0: "LBL_OK", 1: "LBL_EINVAL", 2: "LBL_ENOMEM", 3: "LBL_EDEVICE", 4: "LBL_EBUSY",
                 5: "LBL_ETIMEDOUT", 6: "LBL_ECLOSED"}
 
+ROW_MAJOR = 0
+MORTON = 1
 LOAD_KEEP_INT8 = 0x1
 LOAD_INPUT_DEVICE = 0x2
 LOAD_NO_SPARSE = 0x4
@@ -50,7 +52,7 @@ class LblError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_uint32), ("ny", ctypes.c_uint32), ("cell_m", ctypes.c_float),
-                ("reserved", ctypes.c_uint32)]
+                ("cell_order", ctypes.c_uint32)]
 
 
 class AbsInfo(ctypes.Structure):
@@ -186,13 +188,15 @@ def last_error() -> str:
     return lib().lbl_last_error().decode()
 
 
-def _grid(nx, ny, cell_m=0.0):
-    return Grid(int(nx), int(ny), float(cell_m), 0)
+def _grid(nx, ny, cell_m=0.0, cell_order=ROW_MAJOR):
+    return Grid(int(nx), int(ny), float(cell_m), int(cell_order))
 
 
-def load_abstraction(nx: int, ny: int, row_ptr, col_idx, flags: int = 0, cell_m: float = 0.0) -> int:
+def load_abstraction(nx: int, ny: int, row_ptr, col_idx, flags: int = 0, cell_m: float = 0.0,
+                     cell_order: int = ROW_MAJOR) -> int:
     """Returns an lbl_abs_t handle (int).  row_ptr/col_idx: numpy (host) or,
-    with LOAD_INPUT_DEVICE, device tensors."""
+    with LOAD_INPUT_DEVICE, device tensors.  cell_order: how col_idx (and
+    later the rows of O) number the cells, ROW_MAJOR or MORTON."""
     if isinstance(row_ptr, np.ndarray):
         row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
         col_idx = np.ascontiguousarray(col_idx, np.uint32)
@@ -200,18 +204,19 @@ def load_abstraction(nx: int, ny: int, row_ptr, col_idx, flags: int = 0, cell_m:
     else:
         n_traj = row_ptr.numel() - 1
     h = ctypes.c_void_p()
-    g = _grid(nx, ny, cell_m)
+    g = _grid(nx, ny, cell_m, cell_order)
     _check(lib().lbl_load_abstraction(ctypes.byref(g), n_traj, _addr(row_ptr), _addr(col_idx), flags,
                                       ctypes.byref(h)))
     return h.value
 
 
-def load_abstraction_dense(nx: int, ny: int, T, flags: int = 0, cell_m: float = 0.0) -> int:
+def load_abstraction_dense(nx: int, ny: int, T, flags: int = 0, cell_m: float = 0.0,
+                           cell_order: int = ROW_MAJOR) -> int:
     if isinstance(T, np.ndarray):
         T = np.ascontiguousarray(T, np.uint8)
     n_traj = T.shape[0]
     h = ctypes.c_void_p()
-    g = _grid(nx, ny, cell_m)
+    g = _grid(nx, ny, cell_m, cell_order)
     _check(lib().lbl_load_abstraction_dense(ctypes.byref(g), n_traj, _addr(T), flags, ctypes.byref(h)))
     return h.value
 
@@ -244,11 +249,12 @@ def shapes_array(kind, prop, cx, cy, a, b) -> np.ndarray:
     return out
 
 
-def raster_frame(nx: int, ny: int, cell_m: float, shapes: np.ndarray, n_props: int, O, stream=None) -> None:
+def raster_frame(nx: int, ny: int, cell_m: float, shapes: np.ndarray, n_props: int, O, stream=None,
+                 cell_order: int = ROW_MAJOR) -> None:
     """Rasterize proposition shapes (a SHAPE_DTYPE host array) into the device
-    frame O (n_cells x n_props bytes, row-major cells)."""
+    frame O (n_cells x n_props bytes, cells numbered in cell_order)."""
     shapes = np.ascontiguousarray(shapes, SHAPE_DTYPE)
-    g = _grid(nx, ny, cell_m)
+    g = _grid(nx, ny, cell_m, cell_order)
     ptr = shapes.ctypes.data if len(shapes) else None
     _check(lib().lbl_raster_frame(ctypes.byref(g), float(cell_m), ptr, len(shapes), n_props, _addr(O),
                                   _stream(stream)))
@@ -338,9 +344,9 @@ def serve_stop(s: int) -> None:
     _check(lib().lbl_serve_stop(s))
 
 
-def cell_position(nx: int, ny: int, cell: int) -> tuple[int, int]:
+def cell_position(nx: int, ny: int, cell: int, cell_order: int = ROW_MAJOR) -> tuple[int, int]:
     w, b = ctypes.c_uint32(), ctypes.c_uint32()
-    g = _grid(nx, ny)
+    g = _grid(nx, ny, 0.0, cell_order)
     _check(lib().lbl_cell_position(ctypes.byref(g), cell, ctypes.byref(w), ctypes.byref(b)))
     return w.value, b.value
 

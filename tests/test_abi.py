@@ -62,6 +62,25 @@ def test_cell_order_is_a_bijection_with_tiles_in_words(nx, ny):
     assert len(seen) == nx * ny
 
 
+def test_morton_cell_ids_address_the_same_device_position():
+    """With LBL_MORTON the caller's id is the z-order index of Alg. zcurve (as
+    the oracle's descent computes it); the library must place that cell where
+    the row-major id of the same cell goes."""
+    import oracle
+    for n in (8, 16, 64):
+        d = 2 * (n.bit_length() - 1)
+        seen = set()
+        for iy in range(n):
+            for ix in range(n):
+                z = oracle.zorder([ix + 0.5, iy + 0.5], [0.0, 0.0], [float(n), float(n)], d)
+                wz, bz = lbl.cell_position(n, n, z, lbl.MORTON)
+                assert (wz, bz) == lbl.cell_position(n, n, iy * n + ix), (n, ix, iy, z)
+                seen.add(z)
+        assert seen == set(range(n * n))
+    with pytest.raises(lbl.LblError):
+        lbl.cell_position(64, 64, 64 * 64, lbl.MORTON)
+
+
 def test_invalid_arguments_are_rejected_without_a_device():
     rp = np.array([0, 1], np.uint64)
     ci = np.array([0], np.uint32)
@@ -95,10 +114,14 @@ def test_invalid_arguments_are_rejected_without_a_device():
     h = ctypes.c_void_p()
     st = lbl.lib().lbl_load_abstraction(ctypes.byref(g), 0, rp.ctypes.data, ci.ctypes.data, 0, ctypes.byref(h))
     assert st == lbl.EINVAL and h.value is None
-    # reserved must be zero
-    g = lbl.Grid(8, 8, 0.5, 1)
-    st = lbl.lib().lbl_load_abstraction(ctypes.byref(g), 1, rp.ctypes.data, ci.ctypes.data, 0, ctypes.byref(h))
-    assert st == lbl.EINVAL
+    # cell_order must be known; z-order ids need a square grid of power-of-two side
+    for g in (lbl.Grid(8, 8, 0.5, 2), lbl.Grid(24, 24, 0.5, lbl.MORTON), lbl.Grid(16, 8, 0.5, lbl.MORTON)):
+        st = lbl.lib().lbl_load_abstraction(ctypes.byref(g), 1, rp.ctypes.data, ci.ctypes.data, 0, ctypes.byref(h))
+        assert st == lbl.EINVAL and h.value is None
+        assert "cell_order" in lbl.last_error() or "LBL_MORTON" in lbl.last_error()
+        T1 = np.zeros((1, g.nx * g.ny), np.uint8)
+        st = lbl.lib().lbl_load_abstraction_dense(ctypes.byref(g), 1, T1.ctypes.data, 0, ctypes.byref(h))
+        assert st == lbl.EINVAL and h.value is None
 
 
 def test_batch_and_serve_reject_bad_arguments():
@@ -124,7 +147,8 @@ def test_raster_rejects_bad_arguments_without_a_device():
         lambda: call(good, O=None),
         lambda: call(None, n=3),
         lambda: call(good, grid=lbl.Grid(12, 16, 0.5, 0)),
-        lambda: call(good, grid=lbl.Grid(16, 16, 0.5, 1)),
+        lambda: call(good, grid=lbl.Grid(16, 16, 0.5, 2)),
+        lambda: call(good, grid=lbl.Grid(24, 24, 0.5, lbl.MORTON)),
         lambda: call(good, n_props=0),
         lambda: call(good, n_props=65),
         lambda: call(good, cell=0.0),

@@ -200,12 +200,14 @@ def test_serve_result_same_alone_and_in_the_mix(abstractions):
     try:
         say("alone")
         La = torch.full((x.a.n_traj, 37), 9, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()  # O and L are written before the request is submitted
         assert lbl.serve_wait(s, lbl.serve_submit(s, x.h, Od, 37, La)) == lbl.OK
         alone = La.cpu().numpy()
         say("in the mix")
         mix = requests(abstractions, 30, seed=2)
         Lm = torch.full((x.a.n_traj, 37), 9, dtype=torch.uint8, device="cuda")
         mix.insert(15, (x.h, Od, 37, Lm, want))
+        torch.cuda.synchronize()
         serve_and_check(s, mix, n_threads=4)
         assert np.array_equal(alone, want)
         assert np.array_equal(Lm.cpu().numpy(), alone)
@@ -220,6 +222,7 @@ def test_serve_admission_by_memory(abstractions):
     try:
         Od64 = torch.from_numpy(frames_for(x, 0, 0, n_props=64)).cuda()
         Ld64 = torch.empty((x.a.n_traj, 64), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
         assert lbl.serve_wait(s, lbl.serve_submit(s, x.h, Od64, 64, Ld64)) == lbl.OK
         need = lbl.serve_stats(s)["budget_high_water"]
     finally:

@@ -151,28 +151,32 @@ def test_cfg3_rows_subset_densities(rho):
         lbl.free_abstraction(h)
 
 
-def test_cfg3_full_size_sampled_rows():
-    say("cfg3 full 200k x 512^2 x 64: generate")
+@pytest.fixture(scope="module")
+def cfg3_full():
+    say("cfg3 full 200k x 512^2: generate")
     a = gen.make_abstraction(3)
-    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
-    try:
-        info = lbl.abstraction_info(h)
-        assert info["set_cells"] == int(a.row_ptr[-1])
-        rng = np.random.default_rng(0)
-        rows = np.sort(rng.choice(a.n_traj, 4096, replace=False)).astype(np.uint64)
-        rows[-1] = a.n_traj - 1
-        for rho in (0.01, 0.4):
-            O = gen.make_frame(3, a.grid, 64, frame=1, rho=rho)
-            for name in ("sparse", "bits", "mfma"):
-                say(f"cfg3 full rho={rho} kernel {name}")
-                L = label(h, O, a.n_traj, KERNELS[name])
-                assert_same(L[rows.astype(np.int64)], expect(a, O, rows), f"cfg3-full/{name}/rho{rho}")
-                assert set(np.unique(L)) <= {0, 1}
-                # property at any size: a row with no swept cell has an all-false label
-                empty = np.nonzero(np.diff(a.row_ptr) == 0)[0]
-                assert not L[empty].any()
-    finally:
-        lbl.free_abstraction(h)
+    say("cfg3 full: load with the int8 copy (52 GB)")
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
+    yield a, h
+    lbl.free_abstraction(h)
+
+
+@pytest.mark.parametrize("rho", [0.01, 0.10, 0.40])
+def test_cfg3_full_size_whole_L(cfg3_full, rho):
+    """The headline workload (200,000 x 512^2 x 64), every row and column
+    compared with the oracle, for every kernel, at the three O densities."""
+    a, h = cfg3_full
+    info = lbl.abstraction_info(h)
+    assert info["set_cells"] == int(a.row_ptr[-1])
+    O = gen.make_frame(3, a.grid, 64, frame=1, rho=rho)
+    say(f"cfg3 full rho={rho}: oracle")
+    want = expect(a, O)
+    empty = np.nonzero(np.diff(a.row_ptr) == 0)[0]
+    for name, k in KERNELS.items():
+        say(f"cfg3 full rho={rho} kernel {name}")
+        L = label(h, O, a.n_traj, k)
+        assert_same(L, want, f"cfg3-full/{name}/rho{rho}")
+        assert not L[empty].any()
 
 
 # ------------------------------------------------------------------ edges
@@ -239,6 +243,57 @@ def test_dense_and_device_csr_loads_agree(cfg1):
     finally:
         for h in (h1, h2, h3):
             lbl.free_abstraction(h)
+
+
+def zorder_ids(n):
+    """z-order index (Alg. zcurve, the oracle's descent) of every row-major cell
+    of an n x n grid."""
+    d = 2 * (n.bit_length() - 1)
+    z = np.empty(n * n, np.int64)
+    for iy in range(n):
+        for ix in range(n):
+            z[iy * n + ix] = oracle.zorder([ix + 0.5, iy + 0.5], [0.0, 0.0], [float(n), float(n)], d)
+    assert np.array_equal(np.sort(z), np.arange(n * n))
+    return z
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_morton_cell_ids_give_the_row_major_labels(cfg, cfg1, cfg2):
+    """T and O numbered by z-order index (LBL_MORTON) label exactly as the
+    same T and O numbered row-major."""
+    a = cfg1 if cfg == 1 else cfg2
+    n, n_props = a.grid.n, (8 if cfg == 1 else 32)
+    z = zorder_ids(n)
+    O = gen.make_frame(cfg, a.grid, n_props, frame=3)
+    want = expect(a, O)
+    Oz = np.empty_like(O)
+    Oz[z] = O
+    col_z = z[a.col_idx.astype(np.int64)].astype(np.uint32)
+    say(f"morton cfg{cfg}: csr load")
+    h = lbl.load_abstraction(n, n, a.row_ptr, col_z, lbl.LOAD_KEEP_INT8, cell_order=lbl.MORTON)
+    try:
+        for name, k in KERNELS.items():
+            say(f"morton cfg{cfg} kernel {name}")
+            assert_same(label(h, Oz, a.n_traj, k), want, f"morton/cfg{cfg}/{name}")
+    finally:
+        lbl.free_abstraction(h)
+    if cfg == 1:
+        say("morton cfg1: dense load")
+        Tz = np.zeros_like(a.dense())
+        Tz[:, z] = a.dense()
+        h = lbl.load_abstraction_dense(n, n, Tz, cell_order=lbl.MORTON)
+        try:
+            for k in (lbl.KERNEL_SPARSE, lbl.KERNEL_BITS):
+                assert_same(label(h, Oz, a.n_traj, k), want, "morton/dense")
+        finally:
+            lbl.free_abstraction(h)
+        say("morton cfg1: rasterizer writes z-order rows")
+        sh = gen.frame_shapes(1, a.grid, 8, 3)
+        shapes = lbl.shapes_array(sh.kind, sh.prop, sh.cx, sh.cy, sh.a, sh.b)
+        Or = torch.empty((n * n, 8), dtype=torch.uint8, device="cuda")
+        lbl.raster_frame(n, n, a.grid.res, shapes, 8, Or, cell_order=lbl.MORTON)
+        torch.cuda.synchronize()
+        assert np.array_equal(Or.cpu().numpy(), Oz)
 
 
 def test_errors_on_device():

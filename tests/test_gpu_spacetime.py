@@ -3,8 +3,8 @@
 at about 1% and 90%), and the sparse-only load that holds the largest of
 Table 1's transition systems (1,097,702 rows; 288 GB as bitpacked rows).
 
-Expected labels come only from the oracle (whole L at the small sizes,
-sampled rows at Table 1's sizes); every case prints what it runs first.
+Expected labels come only from the oracle (whole L at every size, Table 1's
+five included); every case prints what it runs first.
 """
 import os
 import sys
@@ -20,7 +20,7 @@ from paper_1810_02612_amd import lbl  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 THREADS = min(16, os.cpu_count() or 1)
-TABLE1_ROWS = (154776, 1097702)
+TABLE1_ROWS = (154776, 295700, 568958, 836276, 1097702)
 
 
 def say(*a):
@@ -54,10 +54,6 @@ def assert_same(got, want, what):
     if not np.array_equal(got, want):
         bad = np.argwhere(got != want)
         raise AssertionError(f"{what}: {len(bad)} labels differ, first at {bad[:5].tolist()}")
-
-
-def sample_rows(n, step=97, tail=200):
-    return np.unique(np.concatenate([np.arange(0, n, step), np.arange(max(0, n - tail), n)])).astype(np.uint64)
 
 
 @pytest.mark.parametrize("n_traj,g", [
@@ -131,13 +127,16 @@ def test_sparse_only_rejects_bitpacked_kernels_and_mixed_batches():
 
 
 @pytest.mark.parametrize("n_traj", TABLE1_ROWS)
-def test_table1_sizes_sampled(n_traj):
+def test_table1_sizes_whole_L(n_traj):
+    """Every transition of each of Table 1's five systems, both propositions
+    together and each alone (as Table 1 times them), against the oracle."""
     g = gen.SpaceTimeGrid()
     say(f"Table 1 size {n_traj}: generating")
     A = gen.spacetime_abstraction(n_traj, g, threads=THREADS)
     O = gen.spacetime_frame(g, 0)
-    rows = sample_rows(n_traj)
-    want = oracle.label_csr(A.row_ptr, A.col_idx, g.n_cells, O, rows=rows, threads=THREADS)
+    say("  oracle")
+    want = oracle.label_csr(A.row_ptr, A.col_idx, g.n_cells, O, threads=THREADS)
+    assert 0 < want[:, 0].mean() < 1 and 0 < want[:, 1].mean() < 1
     say(f"  sparse-only load, {len(A.col_idx)} cells")
     h = load(A, lbl.LOAD_SPARSE_ONLY)
     try:
@@ -145,18 +144,19 @@ def test_table1_sizes_sampled(n_traj):
         assert info["bits_bytes"] == 0 and info["set_cells"] == len(A.col_idx)
         say(f"  label, {info['sparse_entries']} entries")
         L = label(h, O, n_traj)
-        assert_same(L[rows.astype(np.int64)], want, f"{n_traj} rows, sampled")
-        assert set(np.unique(L)) <= {0, 1}
+        assert_same(L, want, f"{n_traj} rows, both propositions")
+        for p in range(2):
+            say(f"  proposition {p} alone")
+            assert_same(label(h, np.ascontiguousarray(O[:, p:p + 1]), n_traj), want[:, p:p + 1],
+                        f"{n_traj} rows, proposition {p} alone")
     finally:
         lbl.free_abstraction(h)
-    del A
     if n_traj == TABLE1_ROWS[0]:
         # the full load (bitpacked rows, 40.6 GB) labels identically
-        A = gen.spacetime_abstraction(n_traj, g, threads=THREADS)
         say("  full load for comparison")
         h = load(A)
         try:
-            assert_same(label(h, O, n_traj), L, "full load, sparse kernel, against sparse-only")
-            assert_same(label(h, O, n_traj, lbl.KERNEL_BITS), L, "full load, bitpacked kernel")
+            assert_same(label(h, O, n_traj), want, "full load, sparse kernel")
+            assert_same(label(h, O, n_traj, lbl.KERNEL_BITS), want, "full load, bitpacked kernel")
         finally:
             lbl.free_abstraction(h)
