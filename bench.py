@@ -56,8 +56,12 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the six-abstraction batched run")
     p.add_argument("--batch-reps", type=int, default=10)
     p.add_argument("--no-serve", action="store_true", help="skip the serving run")
-    p.add_argument("--serve-seconds", type=float, default=5.0, help="seconds per arrival rate")
+    p.add_argument("--serve-seconds", type=float, default=60.0, help="seconds per arrival rate")
     p.add_argument("--serve-rates", default="200,500,1000,2000")
+    p.add_argument("--serve-burst", type=int, default=4000,
+                   help="requests of the closed-loop burst (every client submits as fast as it can)")
+    p.add_argument("--no-configs", action="store_true", help="skip the small and medium configurations")
+    p.add_argument("--no-mall", action="store_true", help="skip the headline over three resident abstractions")
     p.add_argument("--serve-budget-mib", type=int, default=2048)
     p.add_argument("--no-table1", action="store_true", help="skip the time-augmented workloads of Table 1's sizes")
     p.add_argument("--table1-sizes", default="154776,295700,568958,836276,1097702")
@@ -144,6 +148,136 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
             "kernel": "label_" + kernel, "kernel_ms": kernel_ms, "algorithmic_bytes": alg}
 
 
+def mfma_issued_ops(lbl, a, n_props: int, m_tiles: int = 2) -> int:
+    """Multiply-add operations the int8 MFMA kernel issues on this T: a
+    wavefront takes 16 * m_tiles rows and walks the row 8 words (512 cells) at
+    a time, skipping a block whose words are zero in every one of its rows;
+    each block it keeps costs m_tiles x ceil(n_props / 16) x 8 instructions of
+    16 x 16 x 64 multiply-adds (2 operations each)."""
+    n = a.grid.n
+    W = n * n // 64
+    cw = np.fromiter((lbl.cell_position(n, n, c)[0] for c in range(n * n)), np.int64, n * n)
+    rows_per_wave = 16 * m_tiles
+    n_blocks = (W + 7) // 8
+    n_waves = (a.n_traj + rows_per_wave - 1) // rows_per_wave
+    kept = np.zeros(n_waves * n_blocks, bool)
+    rp = a.row_ptr.astype(np.int64)
+    for r0 in range(0, a.n_traj, 16384):
+        r1 = min(a.n_traj, r0 + 16384)
+        cols = a.col_idx[rp[r0]:rp[r1]].astype(np.int64)
+        rows = np.repeat(np.arange(r0, r1, dtype=np.int64), np.diff(rp[r0:r1 + 1]))
+        kept[(rows // rows_per_wave) * n_blocks + cw[cols] // 8] = True
+    nt = (n_props + 15) // 16
+    return int(kept.sum()) * m_tiles * nt * 8 * 2 * 16 * 16 * 64
+
+
+def bench_configs(args, lbl, torch, gen, stream):
+    """The small configuration (1,000 x 64^2 x 8, cache-resident: per-frame
+    latency) and the medium one (50,000 x 256^2 x 32: throughput and the label
+    kernel's HBM roofline), each on the library's default path."""
+    out = {}
+    a = gen.make_abstraction(1)
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
+    Oh = [gen.make_frame(1, a.grid, 8, frame=f) for f in range(8)]
+    Os = [torch.from_numpy(o).cuda() for o in Oh]
+    L = torch.empty((a.n_traj, 8), dtype=torch.uint8, device="cuda")
+    for k in range(10):
+        lbl.label_frame(h, Os[k % 8], 8, L, stream=stream)
+    lat = []
+    for k in range(150):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lbl.label_frame(h, Os[k % 8], 8, L, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+    Lh = np.empty((a.n_traj, 8), np.uint8)
+    host = []
+    for k in range(150):
+        t = time.perf_counter()
+        lbl.label_frame(h, Oh[k % 8], 8, Lh, flags=lbl.HOST_PTRS)
+        host.append(1000 * (time.perf_counter() - t))
+    host = np.array(host)
+    out["small"] = {"workload": "1000 trajectories x 64x64 cells x 8 propositions, O density 5-20%",
+                    "frames": 150, "device_mean_ms": float(lat.mean()), "device_p50_ms": float(np.median(lat)),
+                    "device_p99_ms": float(np.percentile(lat, 99)),
+                    "host_ptrs_mean_ms": float(host.mean()), "host_ptrs_p50_ms": float(np.median(host)),
+                    "host_ptrs_p99_ms": float(np.percentile(host, 99)),
+                    "note": "device: GPU events around one frame's kernels; host_ptrs: O in and L out over PCIe, "
+                            "wall time of the synchronous call"}
+    lbl.free_abstraction(h)
+    log("small", out["small"])
+
+    a = gen.make_abstraction(2)
+    h = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx)
+    info = lbl.abstraction_info(h)
+    Os = [torch.from_numpy(gen.make_frame(2, a.grid, 32, frame=f)).cuda() for f in range(8)]
+    L = torch.empty((a.n_traj, 32), dtype=torch.uint8, device="cuda")
+    for k in range(10):
+        lbl.label_frame(h, Os[k % 8], 32, L, stream=stream)
+    steps = 150
+    wall, _ = timed_steps(lbl, torch, h, Os, 32, L, 0, steps, stream, profile=False)
+    _, prof = timed_steps(lbl, torch, h, Os, 32, L, 0, steps, stream, profile=True)
+    label_ms = prof["label_ms"] / max(1, prof["label_launches"])
+    roof = roofline("sparse", info, a.n_traj, 32, label_ms)
+    roof["traffic"] = None
+    out["medium"] = {"workload": "50000 trajectories x 256x256 cells x 32 propositions, O density 5-20%",
+                     "steps": steps, "ms_per_step": 1000 * wall / steps,
+                     "pairs_per_s": a.n_traj * 32 * steps / wall, "label_kernel_roofline": roof,
+                     "t_row_density": info["set_cells"] / (a.n_traj * a.grid.n_cells)}
+    lbl.free_abstraction(h)
+    log("medium", out["medium"])
+    return out
+
+
+def bench_mall(args, lbl, torch, gen, Os, n_props, stream):
+    """The headline frame over three resident 200,000 x 512^2 abstractions
+    (distinct seeds) taken in turn: their sparse layouts (about 100 MB each)
+    exceed the 256 MB last-level cache together, so T streams from HBM."""
+    hs, infos, n_traj = [], [], None
+    for k in (11, 12, 13):
+        a = gen.make_abstraction(3, abstraction=k)
+        hs.append(lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_SPARSE_ONLY))
+        infos.append(lbl.abstraction_info(hs[-1]))
+        n_traj = a.n_traj
+        del a
+    L = torch.empty((n_traj, n_props), dtype=torch.uint8, device="cuda")
+    for k in range(6):
+        lbl.label_frame(hs[k % 3], Os[k % len(Os)], n_props, L, stream=stream)
+    steps = 150
+
+    def run(profile):
+        torch.cuda.synchronize()
+        if profile:
+            lbl.profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            lbl.label_frame(hs[k % 3], Os[k % len(Os)], n_props, L, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = lbl.profile_read()
+            lbl.profile_enable(False)
+        return dt, prof
+
+    wall, _ = run(False)
+    _, prof = run(True)
+    label_ms = prof["label_ms"] / max(1, prof["label_launches"])
+    mean_info = {k: float(np.mean([i[k] for i in infos])) for k in ("sparse_frame_bytes", "n_words")}
+    mean_info["n_words"] = int(mean_info["n_words"])
+    roof = roofline("sparse", mean_info, n_traj, n_props, label_ms)
+    roof["traffic"] = None
+    for h in hs:
+        lbl.free_abstraction(h)
+    out = {"abstractions": 3, "sparse_bytes_total": int(sum(i["sparse_bytes"] for i in infos)),
+           "ms_per_step": 1000 * wall / steps, "pairs_per_s": n_traj * n_props * steps / wall,
+           "label_kernel_roofline": roof}
+    log("mall", out)
+    return out
+
+
 def load_batch_abstractions(lbl, gen):
     """The six uneven abstractions (10k..200k trajectories on 128^2..512^2 grids)."""
     out = []
@@ -178,13 +312,20 @@ def bench_batch(args, lbl, torch, gen, abss, stream):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / args.batch_reps
 
-    # one frame per launch: the plain bitpacked kernel, and the sparse kernel
-    single_s = per_frame(lbl.KERNEL_BITS)
+    # one frame per launch: the library's default (sparse) kernel, and the
+    # plain bitpacked kernel
     single_sparse_s = per_frame(lbl.KERNEL_SPARSE)
-    # batched: tune the tile for this shape class, then replay the cached graph
+    ref = [Ld.clone() for (_, _, _, Ld) in jobs]
+    single_s = per_frame(lbl.KERNEL_BITS)
+    # batched: tune the launch for this shape class, then replay the cached graph
     lbl.tune_batch(jobs, stream=stream)
+    for (_, _, _, Ld) in jobs:
+        Ld.fill_(5)
     lbl.label_batch(jobs, stream=stream)
     torch.cuda.synchronize()
+    # the batch's labels are the one-frame path's, byte for byte
+    same = sum(int(torch.equal(Ld, r)) for (_, _, _, Ld), r in zip(jobs, ref))
+    tuned = lbl.tune_batch_describe(jobs, stream=stream)
     lbl.profile_enable(True)
     t = time.perf_counter()
     for _ in range(args.batch_reps):
@@ -197,18 +338,25 @@ def bench_batch(args, lbl, torch, gen, abss, stream):
     gpu_ms = prof["batch_ms"] / max(1, prof["batch_launches"])
     return {"frames": len(jobs), "abstractions": [[a.n_traj, a.grid.n] for a, _ in abss],
             "pairs_per_batch": pairs,
-            "one_frame_per_launch": {"ms": 1000 * single_s, "pairs_per_s": pairs / single_s,
-                                     "kernel": "bits"},
-            "one_frame_per_launch_sparse": {"ms": 1000 * single_sparse_s, "pairs_per_s": pairs / single_sparse_s,
-                                            "kernel": "sparse"},
-            "batched": {"ms": 1000 * batch_s, "gpu_ms": gpu_ms, "pairs_per_s": pairs / batch_s},
-            "speedup": single_s / batch_s,
-            "speedup_vs_sparse_per_frame": single_sparse_s / batch_s}
+            "one_frame_per_launch": {"ms": 1000 * single_sparse_s, "pairs_per_s": pairs / single_sparse_s,
+                                     "kernel": "sparse (the library's default)"},
+            "one_frame_per_launch_bits": {"ms": 1000 * single_s, "pairs_per_s": pairs / single_s,
+                                          "kernel": "bits"},
+            "batched": {"ms": 1000 * batch_s, "gpu_ms": gpu_ms, "pairs_per_s": pairs / batch_s,
+                        "launch": tuned},
+            "speedup": single_sparse_s / batch_s,
+            "speedup_vs_bits_per_frame": single_s / batch_s,
+            "jobs_equal_to_one_frame_path": f"{same}/{len(jobs)}"}
 
 
 def bench_serve(args, lbl, torch, gen, abss):
     """Poisson arrivals; each request one frame (8..64 propositions, density
-    5..30%) against one of the six resident abstractions, chosen uniformly."""
+    5..30%) against one of the six resident abstractions, chosen uniformly.
+    Each rate runs for --serve-seconds with batches launched as soon as a
+    stream is free (max_wait_us 0: the lowest latency at these rates).  A
+    closed-loop burst follows: the client submits as fast as it can while
+    up to 48 requests per abstraction are outstanding, and batches wait up to
+    200 us for company, so they form (batches well below requests)."""
     import queue
     import threading
 
@@ -224,18 +372,17 @@ def bench_serve(args, lbl, torch, gen, abss):
     ring = 48
     Lbuf = [[torch.empty(a.n_traj * 64, dtype=torch.uint8, device="cuda") for _ in range(ring)] for a, _ in abss]
     torch.cuda.synchronize()
-    results = []
-    for lam in [float(x) for x in args.serve_rates.split(",")]:
-        s = lbl.serve_start(hbm_budget_bytes=args.serve_budget_mib << 20, max_batch_frames=16, max_wait_us=0,
-                            max_queue=8192, n_streams=3)
+
+    def run(lam, n_req, max_wait_us):
+        s = lbl.serve_start(hbm_budget_bytes=args.serve_budget_mib << 20, max_batch_frames=16,
+                            max_wait_us=max_wait_us, max_queue=8192, n_streams=3)
         free = [queue.Queue() for _ in abss]
         for q in free:
             for k in range(ring):
                 q.put(k)
         inflight = queue.Queue()
         samples, errors = [], []
-        n_req = int(lam * args.serve_seconds)
-        gaps = rng.exponential(1.0 / lam, n_req)
+        gaps = rng.exponential(1.0 / lam, n_req) if lam else np.zeros(n_req)
         choice = rng.integers(0, len(abss), n_req)
         fpick = rng.integers(0, 8, n_req)
         sample_every = 100
@@ -282,22 +429,33 @@ def bench_serve(args, lbl, torch, gen, abss):
             t.join()
         st = lbl.serve_stats(s)
         lbl.serve_stop(s)
-        # identity: each sampled request labeled alone gives the same bytes
+        # identity: each sampled request labeled alone (the library's default
+        # one-frame path) gives the same bytes
         same = 0
         for i, f, Lmix in samples:
             Od, n_props = pool[i][f]
             La = torch.empty_like(Lmix)
-            lbl.label_frame(abss[i][1], Od, n_props, La, flags=lbl.KERNEL_BITS)
+            lbl.label_frame(abss[i][1], Od, n_props, La)
             torch.cuda.synchronize()
             same += int(torch.equal(La, Lmix))
-        results.append({"rate_per_s": lam, "seconds": args.serve_seconds, "submitted": st["submitted"],
-                        "completed": st["completed"], "rejected": st["rejected"], "failed": st["failed"],
-                        "batches": st["batches"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                        "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
-                        "req_per_s": st["completed"] / st["wall_s"], "pairs_per_s": st["pairs_per_s"],
-                        "max_in_flight": st["max_in_flight"], "budget_high_water": st["budget_high_water"],
-                        "identity_checked": len(samples), "identity_same": same, "errors": errors[:3]})
-        log("serve", results[-1])
+        out = {"rate_per_s": lam if lam else "closed loop", "max_wait_us": max_wait_us,
+               "submitted": st["submitted"], "completed": st["completed"], "rejected": st["rejected"],
+               "failed": st["failed"], "batches": st["batches"],
+               "frames_per_batch": st["completed"] / max(1, st["batches"]), "p50_ms": st["p50_ms"],
+               "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"], "wall_s": st["wall_s"],
+               "req_per_s": st["completed"] / st["wall_s"], "pairs_per_s": st["pairs_per_s"],
+               "max_in_flight": st["max_in_flight"], "budget_high_water": st["budget_high_water"],
+               "identity_checked": len(samples), "identity_same": same, "errors": errors[:3]}
+        log("serve", out)
+        return out
+
+    results = []
+    for lam in [float(x) for x in args.serve_rates.split(",") if x]:
+        r = run(lam, int(lam * args.serve_seconds), 0)
+        r["seconds"] = args.serve_seconds
+        results.append(r)
+    if args.serve_burst > 0:
+        results.append(run(None, args.serve_burst, 200))
     return results
 
 
@@ -526,6 +684,7 @@ def main():
         sweep = []
         h8 = lbl.load_abstraction(a.grid.n, a.grid.n, a.row_ptr, a.col_idx, lbl.LOAD_KEEP_INT8)
         info8 = lbl.abstraction_info(h8)
+        mfma_ops = mfma_issued_ops(lbl, a, n_props)
         for rho in (0.01, 0.10, 0.40):
             Ox = [torch.from_numpy(gen.make_frame(3, a.grid, n_props, frame=100 + f, rho=rho)).cuda()
                   for f in range(2)]
@@ -535,13 +694,27 @@ def main():
                 w, pr = timed_steps(lbl, torch, h8, Ox, n_props, L, kf, args.sweep_steps, stream)
                 kms = pr["label_ms"] / max(1, pr["label_launches"])
                 r = roofline(name, info8, a.n_traj, n_props, kms)
+                row = {"rho": rho, "kernel": name, "kernel_ms": kms, "step_ms": 1000 * w / args.sweep_steps,
+                       "label_kernel_pairs_per_s": pairs / (kms * 1e-3), "roofline_bound": r["bound"],
+                       "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
+                if name == "mfma":
+                    # only the blocks the kernel multiplies count, not the dense
+                    # 2 N_t N_c N_p of the product
+                    row["achieved"] = mfma_ops / (kms * 1e-3) / 1e12
+                    row["frac"] = row["achieved"] / INT8_PEAK_TOPS
+                    row["issued_ops"] = mfma_ops
+                    row["dense_equivalent_ops"] = r["algorithmic_ops"]
                 # step_ms is taken with per-kernel events on, so it includes their cost
-                sweep.append({"rho": rho, "kernel": name, "kernel_ms": kms, "step_ms": 1000 * w / args.sweep_steps,
-                              "label_kernel_pairs_per_s": pairs / (kms * 1e-3), "roofline_bound": r["bound"],
-                              "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]})
+                sweep.append(row)
                 log("sweep", sweep[-1])
         lbl.free_abstraction(h8)
         out["kernel_sweep"] = sweep
+
+    if not args.no_mall:
+        out["beyond_mall"] = bench_mall(args, lbl, torch, gen, Os, n_props, stream)
+
+    if not args.no_configs:
+        out["configs"] = bench_configs(args, lbl, torch, gen, stream)
 
     if not (args.no_batch and args.no_serve):
         log("load the six batch abstractions")

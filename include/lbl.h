@@ -161,9 +161,10 @@ typedef struct {
     uint64_t set_cells;      /* distinct (trajectory, cell) pairs set in T */
     uint64_t sparse_entries; /* (row, word) entries of the sparse layout (0 if not built) */
     uint64_t sparse_bytes;   /* device bytes of the sparse layout (entries and tilings) */
-    uint64_t sparse_frame_bytes; /* bytes one frame reads from it: every entry
-                                    (16-bit row, 64-bit word) and the one-frame
-                                    tiling's task and round tables */
+    uint64_t sparse_frame_bytes; /* bytes one frame's label kernel reads from it:
+                                    every entry (16-bit row, 64-bit word), the
+                                    one-frame tiling's task and round tables and
+                                    the rows of its compact partial slots */
     uint32_t sparse_tiles;   /* workgroups of a one-frame launch */
     uint32_t sparse_row_block; /* rows per row block of the sparse layout */
 } lbl_abs_info;
@@ -203,11 +204,20 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
  * further passes in the same launch).  Workgroups pull (abstraction, row
  * range) items from a queue, largest first.
  *
- * The whole pipeline of a batch (O packing, labeling) is recorded once as a
- * HIP graph keyed by (hip_stream, jobs) and replayed when the same batch is
- * submitted again on that stream; the graph owns its tables and packed masks
- * (up to 8 graphs are cached; the oldest is released after a device
- * synchronization).  Results are identical to labeling each job alone.
+ * The whole pipeline of a batch (O packing, labeling, label bytes) is
+ * recorded once as a HIP graph keyed by (hip_stream, jobs, launch choice)
+ * and replayed when the same batch is submitted again on that stream; the
+ * graph owns its tables and packed masks (up to 8 graphs are cached; the
+ * oldest is released after a device synchronization).  Results are
+ * identical to labeling each job alone.
+ *
+ * Jobs on one abstraction are placed into 64-column lane groups first-fit by
+ * decreasing proposition count (a job never spans two lane groups).  With
+ * the sparse layout on every abstraction, one wavefront per (word, lane
+ * group) builds the nibble tables, one workgroup per CU pulls (tile, lane
+ * group) items from per-XCD queues (items reading the same tables share an
+ * XCD), and one wavefront per 64 rows of a lane group writes each job's
+ * label bytes as one contiguous block.
  *
  * Errors: as lbl_label_frame for every job, plus LBL_EINVAL for n_jobs == 0,
  * nonzero flags, or a batch mixing an abstraction without the sparse layout
@@ -276,12 +286,22 @@ lbl_status lbl_raster_frame(const lbl_grid *grid, double cell_m, const lbl_shape
  */
 lbl_status lbl_tune(lbl_abs_t a, const uint8_t *O_sample, uint32_t n_props, uint32_t density_pct,
                     void *hip_stream);
-/* Time the batch kernel's tile shapes (rows per work item, wavefronts per
- * workgroup, loads in flight) on this batch and record the fastest for its
- * shape class (the multiset of (words per row, lane groups) of its passes);
- * later lbl_label_batch calls of that class use it.  Runs the batch several
+/* Time the batch's launch choices on this batch and record the fastest for
+ * its shape class (whether every abstraction has the sparse layout, and the
+ * multiset of (words per row, lane groups) of its passes); later
+ * lbl_label_batch calls of that class use it, and the graph cached for
+ * these jobs is rebuilt if it was made for another choice.  Sparse batches:
+ * the tiling of the layout (the one-frame tiling, or 1, 2, 4, 8 tiles per row
+ * block) and the launch (persistent workgroups pulling tiles from per-XCD
+ * queues, or one workgroup per tile).  Bitpacked batches: rows per work
+ * item, wavefronts per workgroup, loads in flight.  Runs the batch several
  * times (the jobs' L buffers are overwritten); synchronizes hip_stream. */
 lbl_status lbl_tune_batch(const lbl_job *jobs, size_t n_jobs, void *hip_stream);
+/* Describe into buf (NUL-terminated) the shape class of a batch and the
+ * launch choice lbl_label_batch would use for it on hip_stream, followed by
+ * "cached" if a graph for these jobs with that choice exists, else "not
+ * built".  Host only; launches nothing. */
+lbl_status lbl_tune_batch_describe(const lbl_job *jobs, size_t n_jobs, void *hip_stream, char *buf, size_t buf_len);
 lbl_status lbl_tune_save(const char *path);
 lbl_status lbl_tune_load(const char *path);
 /* Describe the choice AUTO makes for (a, n_props) into buf (NUL-terminated). */

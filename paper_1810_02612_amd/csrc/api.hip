@@ -424,8 +424,10 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
         const uint64_t entry_bytes = sp.nnz * (sizeof(uint16_t) + sizeof(uint64_t));
         out->sparse_entries = sp.nnz;
         out->sparse_bytes = entry_bytes + sp.round_bytes;
+        // the one-frame label kernel's reads of the layout: entries, its
+        // tasks and rounds, and the local rows of its compact partial slots
         out->sparse_frame_bytes = entry_bytes + (uint64_t)t.n_tiles * kTileWaves * sizeof(SpTask) +
-                                  t.n_rounds * sizeof(SpRound);
+                                  t.n_rounds * sizeof(SpRound) + t.n_slots * sizeof(uint16_t);
         out->sparse_tiles = t.n_tiles;
         out->sparse_row_block = kRowBlock;
     }

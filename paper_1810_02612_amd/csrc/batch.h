@@ -17,6 +17,17 @@ struct LaneDesc {
     uint32_t pad;
 };
 
+// One job's columns inside a lane group.  Jobs are packed into lane groups
+// first-fit by decreasing proposition count, so a job's columns never span
+// two lane groups: lane group gi holds whole jobs, job s at columns
+// [bit, bit + n_props).
+struct SegDesc {
+    const uint8_t *O;  // the job's O (cell c's propositions at O + c * n_props)
+    uint8_t *L;        // the job's L (row t at L + t * n_props)
+    uint32_t n_props;  // the job's proposition count: the row pitch of O and L
+    uint32_t bit;      // first column of the job inside its lane group
+};
+
 // Per abstraction group: all jobs on one abstraction, propositions
 // concatenated into G64 groups of 64 lanes.
 struct GroupDesc {
@@ -26,6 +37,8 @@ struct GroupDesc {
                               // (64 cells each); sparse plans: [n_words][G64][256] nibble
                               // tables
     const LaneDesc *lanes;    // [G64][64]
+    const SegDesc *segs;      // the jobs of lane group gi: segs[lg_seg[gi] .. lg_seg[gi + 1])
+    const uint32_t *lg_seg;   // [G64 + 1]
     uint64_t n_traj;
     uint32_t row_stride;
     uint32_t n_words;
@@ -60,10 +73,22 @@ struct WorkItem {
     uint64_t row0, row1;
 };
 
+// Launch choices of a batch.  Bitpacked plans use unroll, waves_per_block
+// and rows_per_item; sparse plans use tiling (0: the plan's default; else
+// 1 + the index of the layout's tiling: 1 = the one-frame tiling, 2..5 = 1,
+// 2, 4, 8 tiles per row block) and persistent (1: one workgroup per CU
+// pulling tiles from per-XCD queues; 0: one workgroup per tile).
 struct BatchTile {
     int unroll = 8;
     int waves_per_block = 4;
     int rows_per_item = 128;
+    int tiling = 0;
+    int persistent = 1;
+    bool operator==(const BatchTile &o) const
+    {
+        return unroll == o.unroll && waves_per_block == o.waves_per_block && rows_per_item == o.rows_per_item &&
+               tiling == o.tiling && persistent == o.persistent;
+    }
 };
 
 struct JobRef {
@@ -78,6 +103,9 @@ struct BatchPlan {
     std::vector<GroupDesc> groups;  // Ow and lanes fields are offsets until bound
     std::vector<LaneDesc> lanes;    // all groups' lane tables, concatenated
     std::vector<size_t> lane_off;   // first lane of each group
+    std::vector<SegDesc> segs;      // all groups' job segments, by group then lane group
+    std::vector<uint32_t> lg_seg;   // per group G64 + 1 entries (absolute indices into segs)
+    std::vector<size_t> lgs_off;    // first lg_seg entry of each group
     std::vector<size_t> ow_off;     // byte offset of each group's Ow in the Ow region
     std::vector<WorkItem> items;
     size_t ow_bytes = 0;
@@ -90,10 +118,13 @@ struct BatchPlan {
     bool sparse = false;
     std::vector<size_t> p_off;      // byte offset of each group's partials in the P region
     size_t p_bytes = 0;
-    std::vector<TileItem> tiles;
+    std::vector<TileItem> tiles;    // in queue order: XCD x's queue is tiles[xcd_start[x] .. xcd_start[x + 1])
+    std::vector<uint32_t> xcd_start;  // kXcds + 1 entries (sparse plans)
+    std::vector<uint32_t> launch;   // one-workgroup-per-tile launches: workgroup b runs tiles[launch[b]]
     std::vector<CombineItem> combines;
     std::vector<const lbl_abs *> group_abs;  // abstraction of each group
-    int tiling = 0;                 // sparse: index of the tilings every pass uses
+    int default_tiling = 1;         // sparse: tiling index used when the tile does not choose one
+    int tiling = 0;                 // sparse: index of the tilings every pass uses (set by plan_finalize)
 
     bool finalized = false;         // tile set and items made
 
@@ -122,12 +153,26 @@ struct BatchBuffers {
     uint32_t *d_counter = nullptr;
     uint64_t *d_ow = nullptr;
     TileItem *d_tiles = nullptr;
+    uint32_t *d_launch = nullptr;
+    uint32_t *d_xcd_start = nullptr;
+    uint32_t *d_queues = nullptr;   // kXcds queue counters (zeroed by a kernel before each launch)
     CombineItem *d_combines = nullptr;
+    SegDesc *d_segs = nullptr;
+    uint32_t *d_lg_seg = nullptr;
     uint64_t *d_p = nullptr;
 };
 
 // Sparse batch kernels (defined with the sparse layout's kernels).
-hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, uint32_t n_tiles, hipStream_t s);
+// Pack: one wavefront per (group, word, lane group) -> the word's nibble
+// tables for the lane group's columns.
+hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const uint64_t *d_prefix, uint32_t n_groups,
+                                    uint64_t n_units, hipStream_t s);
+// Tiles: persistent (one workgroup per CU, per-XCD queues with stealing;
+// d_queues zeroed first) or one workgroup per tile in launch order.
+hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, const uint32_t *d_launch,
+                              uint32_t n_tiles, hipStream_t s);
+hipError_t launch_tiles_batch_queue(const GroupDesc *d_groups, const TileItem *d_tiles, const uint32_t *d_xcd_start,
+                                    uint32_t *d_queues, uint32_t n_workgroups, hipStream_t s);
 hipError_t launch_combine_batch(const GroupDesc *d_groups, const CombineItem *d_items, uint32_t n_items,
                                 hipStream_t s);
 
@@ -146,5 +191,9 @@ int device_cu_count();
 
 // Tile recorded by lbl_tune_batch for a shape class (the default if none).
 BatchTile batch_tile_for(const std::string &shape_key);
+void set_batch_tile(const std::string &shape_key, const BatchTile &t);
+// Every recorded (shape class, tile) pair, for the tune cache file.
+std::vector<std::pair<std::string, BatchTile>> batch_tiles();
+std::string batch_tile_name(const BatchPlan &p);
 
 }  // namespace lbl

@@ -35,12 +35,15 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int src)
 // Zero the work counter (a kernel, not a memset node, so graph replays are safe).
 __global__ void k_zero(uint32_t *counter) { *counter = 0u; }
 
-// One wavefront per (group, word, lane group): lane l packs the 64 cells of
-// the word for the proposition column that lane (gi, l) stands for.  With
-// PER_CELL the 64 x 64 bit block is transposed across the wavefront (64
-// ballots) so that lane b holds the mask of columns met by cell b, and the
-// word's nibble tables (the layout the sparse kernels read) are written.
-template <bool PER_CELL>
+// Zero n counters (n <= 64).
+__global__ void k_zero_n(uint32_t *counters, uint32_t n)
+{
+    if (threadIdx.x < n) counters[threadIdx.x] = 0u;
+}
+
+// Bitpacked plans: one wavefront per (group, word, lane group): lane l packs
+// the 64 cells of the word for the proposition column that lane (gi, l)
+// stands for.
 __global__ void __launch_bounds__(256)
 k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
              uint64_t n_units)
@@ -60,17 +63,7 @@ k_pack_batch(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ 
 #pragma unroll 16
             for (uint32_t b = 0; b < 64; ++b) m |= (uint64_t)(d.O[(uint64_t)wc[b] * d.n_props] != 0) << b;
         }
-        if (PER_CELL) {
-            uint64_t t = 0;
-#pragma unroll
-            for (uint32_t b = 0; b < 64; ++b) {
-                const uint64_t col = __ballot((m >> b) & 1ull);  // bit l: column l meets cell b
-                t = lane == b ? col : t;
-            }
-            write_tables(t, g.Ow + ((uint64_t)w * g.G64 + gi) * 256, lane);
-        } else {
-            g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
-        }
+        g.Ow[((uint64_t)w * g.G64 + gi) * 64 + lane] = m;
     }
 }
 
@@ -172,7 +165,9 @@ size_t batch_table_bytes(const BatchPlan &p)
 {
     return up256(p.groups.size() * sizeof(GroupDesc)) + up256(p.items.size() * sizeof(WorkItem)) +
            up256(p.lanes.size() * sizeof(LaneDesc)) + up256((p.groups.size() + 1) * sizeof(uint64_t)) + 256 +
-           up256(p.tiles.size() * sizeof(TileItem)) + up256(p.combines.size() * sizeof(CombineItem));
+           up256(p.tiles.size() * sizeof(TileItem)) + up256(p.launch.size() * sizeof(uint32_t)) +
+           up256(p.xcd_start.size() * sizeof(uint32_t)) + up256(p.combines.size() * sizeof(CombineItem)) +
+           up256(p.segs.size() * sizeof(SegDesc)) + up256(p.lg_seg.size() * sizeof(uint32_t));
 }
 
 size_t BatchPlan::device_bytes() const { return batch_table_bytes(*this) + ow_bytes + p_bytes; }
@@ -201,22 +196,35 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
     BatchPlan &p = *out;
     p = BatchPlan{};
     p.sparse = all_sparse;
+    const uint32_t max_g = LBL_BATCH_MAX_PROPS / 64;
     std::vector<std::string> keys;
     for (lbl_abs *a : order) {
-        const auto &js = by_abs[a];
-        size_t k = 0;
-        while (k < js.size()) {
-            // one pass: consecutive jobs while the concatenated columns fit
-            uint32_t P = 0;
-            size_t k1 = k;
-            while (k1 < js.size() && P + jobs[js[k1]].n_props <= LBL_BATCH_MAX_PROPS) P += jobs[js[k1++]].n_props;
+        // first-fit by decreasing proposition count into 64-column lane
+        // groups: a job's columns never span two lane groups
+        std::vector<size_t> js = by_abs[a];
+        std::stable_sort(js.begin(), js.end(), [&](size_t x, size_t y) { return jobs[x].n_props > jobs[y].n_props; });
+        std::vector<uint32_t> used;                 // columns taken in each lane group
+        std::vector<std::vector<size_t>> members;   // jobs of each lane group, in placement order
+        for (size_t j : js) {
+            size_t b = 0;
+            while (b < used.size() && used[b] + jobs[j].n_props > 64) ++b;
+            if (b == used.size()) {
+                used.push_back(0);
+                members.emplace_back();
+            }
+            members[b].push_back(j);
+            used[b] += jobs[j].n_props;
+        }
+        // passes of at most max_g lane groups
+        for (size_t b0 = 0; b0 < members.size(); b0 += max_g) {
+            const size_t b1 = std::min(members.size(), b0 + max_g);
             GroupDesc g{};
             g.T = a->T_bits;
             g.word_cell = a->d_word_cell;
             g.n_traj = a->n_traj;
             g.row_stride = a->row_stride;
             g.n_words = a->n_words;
-            g.G64 = (P + 63) / 64;
+            g.G64 = (uint32_t)(b1 - b0);
             if (p.sparse) {
                 g.n_rb = a->sp->n_rb;
                 g.sp_row = a->sp->row;
@@ -225,12 +233,20 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             }
             p.lane_off.push_back(p.lanes.size());
             p.lanes.resize(p.lanes.size() + (size_t)g.G64 * 64, LaneDesc{nullptr, nullptr, 0, 0});
-            size_t q = p.lane_off.back();
-            for (size_t m = k; m < k1; ++m) {
-                const JobRef &r = jobs[js[m]];
-                for (uint32_t c = 0; c < r.n_props; ++c, ++q) p.lanes[q] = LaneDesc{r.O + c, r.L + c, r.n_props, 0};
-                p.pairs += a->n_traj * r.n_props;
+            p.lgs_off.push_back(p.lg_seg.size());
+            for (size_t b = b0; b < b1; ++b) {
+                p.lg_seg.push_back((uint32_t)p.segs.size());
+                uint32_t bit = 0;
+                for (size_t j : members[b]) {
+                    const JobRef &r = jobs[j];
+                    p.segs.push_back(SegDesc{r.O, r.L, r.n_props, bit});
+                    const size_t q = p.lane_off.back() + (b - b0) * 64 + bit;
+                    for (uint32_t c = 0; c < r.n_props; ++c) p.lanes[q + c] = LaneDesc{r.O + c, r.L + c, r.n_props, 0};
+                    bit += r.n_props;
+                    p.pairs += a->n_traj * r.n_props;
+                }
             }
+            p.lg_seg.push_back((uint32_t)p.segs.size());
             p.ow_off.push_back(p.ow_bytes);
             // bitpacked plans: masks [w][G64][64 columns]; sparse plans:
             // nibble tables [w][G64][256]
@@ -240,25 +256,54 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             p.groups.push_back(g);
             p.group_abs.push_back(a);
             keys.push_back("W" + std::to_string(a->n_words) + "G" + std::to_string(g.G64));
-            k = k1;
         }
     }
     std::sort(keys.begin(), keys.end());
     for (auto &s : keys) p.shape_key += s + ";";
     if (p.sparse) {
-        // the coarsest tiling (fewest partials) that still gives every CU
-        // about two tile workgroups
+        // default: the coarsest tiling (fewest partials) that still gives
+        // every CU about two tile workgroups
         const uint64_t want = 2ull * (uint64_t)device_cu_count();
-        p.tiling = kBatchTilings;
+        p.default_tiling = kBatchTilings;
         for (int t = 1; t <= kBatchTilings; ++t) {
             uint64_t n = 0;
             for (size_t g = 0; g < p.groups.size(); ++g)
                 n += (uint64_t)p.groups[g].G64 * p.group_abs[g]->sp->tilings[t].n_tiles;
             if (n >= want) {
-                p.tiling = t;
+                p.default_tiling = t;
                 break;
             }
         }
+        p.shape_key = "sparse;" + p.shape_key;
+    }
+    return LBL_OK;
+}
+
+std::string batch_tile_name(const BatchPlan &p)
+{
+    char buf[128];
+    if (p.sparse)
+        snprintf(buf, sizeof(buf), "sparse(tiling=%d,persistent=%d)", p.tiling, p.tile.persistent ? 1 : 0);
+    else
+        snprintf(buf, sizeof(buf), "bits(unroll=%d,waves=%d,rows=%d)", p.tile.unroll, p.tile.waves_per_block,
+                 p.tile.rows_per_item);
+    return buf;
+}
+
+void plan_finalize(BatchPlan &p, const BatchTile &tile)
+{
+    p.tile = tile;
+    p.items.clear();
+    p.tiles.clear();
+    p.launch.clear();
+    p.xcd_start.clear();
+    p.combines.clear();
+    p.p_off.clear();
+    p.p_bytes = 0;
+    std::vector<uint32_t> idx(p.groups.size());
+    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    if (p.sparse) {
+        p.tiling = tile.tiling >= 1 && tile.tiling <= kBatchTilings + 1 ? tile.tiling - 1 : p.default_tiling;
         for (size_t g = 0; g < p.groups.size(); ++g) {
             GroupDesc &d = p.groups[g];
             const SpTiling &tl = p.group_abs[g]->sp->tilings[p.tiling];
@@ -269,31 +314,58 @@ lbl_status plan_batch(const JobRef *jobs, size_t n_jobs, int device, BatchPlan *
             p.p_off.push_back(p.p_bytes);
             p.p_bytes += up256((size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t));
         }
-        p.shape_key = "sparse" + std::to_string(p.tiling) + ";" + p.shape_key;
-    }
-    return LBL_OK;
-}
-
-void plan_finalize(BatchPlan &p, const BatchTile &tile)
-{
-    p.tile = tile;
-    p.items.clear();
-    p.tiles.clear();
-    p.combines.clear();
-    std::vector<uint32_t> idx(p.groups.size());
-    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    if (p.sparse) {
-        // tiles of the passes with the most entries per tile first
-        auto cost = [&](uint32_t g) {
-            const GroupDesc &d = p.groups[g];
-            return (double)(d.max_entry + 1) / (double)d.n_tiles;
+        // Tiles that read the same nibble tables (same pass, lane group and
+        // position of the tile inside its row block, hence about the same
+        // word range) share an XCD queue, so that the tables stay in that
+        // XCD's L2.  Table sets go to the least loaded XCD, costliest first;
+        // each queue runs its costliest tiles first.
+        struct Set {
+            double cost;
+            std::vector<TileItem> items;
         };
-        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost(x) > cost(y); });
-        for (uint32_t g : idx) {
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Set> sets;
+        for (uint32_t g = 0; g < p.groups.size(); ++g) {
             const GroupDesc &d = p.groups[g];
-            for (uint32_t t = 0; t < d.n_tiles; ++t)
-                for (uint32_t gi = 0; gi < d.G64; ++gi) p.tiles.push_back(TileItem{g, t, gi, 0});
+            const SpTiling &tl = p.group_abs[g]->sp->tilings[p.tiling];
+            const double c = (double)(d.max_entry + 1) / (double)d.n_tiles;
+            for (uint32_t rb = 0; rb + 1 < tl.rb_tile_host.size(); ++rb)
+                for (uint32_t t = tl.rb_tile_host[rb]; t < tl.rb_tile_host[rb + 1]; ++t)
+                    for (uint32_t gi = 0; gi < d.G64; ++gi) {
+                        Set &st = sets[std::make_tuple(g, gi, t - tl.rb_tile_host[rb])];
+                        st.cost += c;
+                        st.items.push_back(TileItem{g, t, gi, 0});
+                    }
         }
+        std::vector<Set *> order;
+        for (auto &kv : sets) order.push_back(&kv.second);
+        std::stable_sort(order.begin(), order.end(), [](const Set *x, const Set *y) { return x->cost > y->cost; });
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<std::vector<std::pair<double, TileItem>>> q(kXcds);
+        for (Set *st : order) {
+            const size_t x = std::min_element(load.begin(), load.end()) - load.begin();
+            load[x] += st->cost;
+            const double c = st->cost / st->items.size();
+            for (const TileItem &it : st->items) q[x].push_back({c, it});
+        }
+        p.xcd_start.push_back(0);
+        for (uint32_t x = 0; x < kXcds; ++x) {
+            std::stable_sort(q[x].begin(), q[x].end(),
+                             [](const std::pair<double, TileItem> &a, const std::pair<double, TileItem> &b) {
+                                 return a.first > b.first;
+                             });
+            for (auto &e : q[x]) p.tiles.push_back(e.second);
+            p.xcd_start.push_back((uint32_t)p.tiles.size());
+        }
+        // one workgroup per tile: workgroup b runs on XCD b % kXcds, so the
+        // queues are interleaved (a queue that runs out hands its slots to
+        // the others)
+        std::vector<uint32_t> pos(p.xcd_start.begin(), p.xcd_start.end() - 1);
+        while (p.launch.size() < p.tiles.size())
+            for (uint32_t x = 0; x < kXcds; ++x) {
+                uint32_t y = x;
+                for (uint32_t k = 0; k < kXcds && pos[y] >= p.xcd_start[y + 1]; ++k) y = (x + k) % kXcds;
+                if (pos[y] < p.xcd_start[y + 1]) p.launch.push_back(pos[y]++);
+            }
         const uint64_t R = 512;  // rows per combine item (a multiple of 64)
         for (uint32_t g = 0; g < p.groups.size(); ++g)
             for (uint32_t gi = 0; gi < p.groups[g].G64; ++gi)
@@ -314,20 +386,23 @@ lbl_status bind_batch(const BatchPlan &p, uint8_t *base, size_t capacity, BatchB
 {
     LBL_REQUIRE(p.finalized, "batch plan bound before it was finalized");
     size_t off = 0;
-    const size_t o_groups = off;
-    off += up256(p.groups.size() * sizeof(GroupDesc));
-    const size_t o_items = off;
-    off += up256(p.items.size() * sizeof(WorkItem));
-    const size_t o_lanes = off;
-    off += up256(p.lanes.size() * sizeof(LaneDesc));
-    const size_t o_prefix = off;
-    off += up256((p.groups.size() + 1) * sizeof(uint64_t));
-    const size_t o_counter = off;
+    auto region = [&](size_t bytes) {
+        const size_t o = off;
+        off += up256(bytes);
+        return o;
+    };
+    const size_t o_groups = region(p.groups.size() * sizeof(GroupDesc));
+    const size_t o_items = region(p.items.size() * sizeof(WorkItem));
+    const size_t o_lanes = region(p.lanes.size() * sizeof(LaneDesc));
+    const size_t o_prefix = region((p.groups.size() + 1) * sizeof(uint64_t));
+    const size_t o_counter = off;  // the work counter and the kXcds queue counters
     off += 256;
-    const size_t o_tiles = off;
-    off += up256(p.tiles.size() * sizeof(TileItem));
-    const size_t o_combines = off;
-    off += up256(p.combines.size() * sizeof(CombineItem));
+    const size_t o_tiles = region(p.tiles.size() * sizeof(TileItem));
+    const size_t o_launch = region(p.launch.size() * sizeof(uint32_t));
+    const size_t o_xcd = region(p.xcd_start.size() * sizeof(uint32_t));
+    const size_t o_combines = region(p.combines.size() * sizeof(CombineItem));
+    const size_t o_segs = region(p.segs.size() * sizeof(SegDesc));
+    const size_t o_lgs = region(p.lg_seg.size() * sizeof(uint32_t));
     const size_t o_ow = off;
     const size_t o_p = o_ow + p.ow_bytes;
     const size_t total = o_p + p.p_bytes;
@@ -342,8 +417,13 @@ lbl_status bind_batch(const BatchPlan &p, uint8_t *base, size_t capacity, BatchB
     b->d_lanes = reinterpret_cast<LaneDesc *>(base + o_lanes);
     b->d_pack_prefix = reinterpret_cast<uint64_t *>(base + o_prefix);
     b->d_counter = reinterpret_cast<uint32_t *>(base + o_counter);
+    b->d_queues = b->d_counter + 1;
     b->d_tiles = reinterpret_cast<TileItem *>(base + o_tiles);
+    b->d_launch = reinterpret_cast<uint32_t *>(base + o_launch);
+    b->d_xcd_start = reinterpret_cast<uint32_t *>(base + o_xcd);
     b->d_combines = reinterpret_cast<CombineItem *>(base + o_combines);
+    b->d_segs = reinterpret_cast<SegDesc *>(base + o_segs);
+    b->d_lg_seg = reinterpret_cast<uint32_t *>(base + o_lgs);
     b->d_ow = reinterpret_cast<uint64_t *>(base + o_ow);
     b->d_p = reinterpret_cast<uint64_t *>(base + o_p);
     img->assign(o_ow, 0);
@@ -352,15 +432,24 @@ lbl_status bind_batch(const BatchPlan &p, uint8_t *base, size_t capacity, BatchB
     for (size_t g = 0; g < gs.size(); ++g) {
         gs[g].Ow = reinterpret_cast<uint64_t *>(base + o_ow + p.ow_off[g]);
         gs[g].lanes = b->d_lanes + p.lane_off[g];
+        gs[g].segs = b->d_segs;
+        gs[g].lg_seg = b->d_lg_seg + p.lgs_off[g];
         if (p.sparse) gs[g].P = reinterpret_cast<uint64_t *>(base + o_p + p.p_off[g]);
         prefix[g + 1] = prefix[g] + (uint64_t)gs[g].n_words * gs[g].G64;
     }
-    memcpy(img->data() + o_groups, gs.data(), gs.size() * sizeof(GroupDesc));
-    memcpy(img->data() + o_items, p.items.data(), p.items.size() * sizeof(WorkItem));
-    memcpy(img->data() + o_lanes, p.lanes.data(), p.lanes.size() * sizeof(LaneDesc));
-    memcpy(img->data() + o_prefix, prefix.data(), prefix.size() * sizeof(uint64_t));
-    memcpy(img->data() + o_tiles, p.tiles.data(), p.tiles.size() * sizeof(TileItem));
-    memcpy(img->data() + o_combines, p.combines.data(), p.combines.size() * sizeof(CombineItem));
+    auto put = [&](size_t o, const void *src, size_t n) {
+        if (n) memcpy(img->data() + o, src, n);
+    };
+    put(o_groups, gs.data(), gs.size() * sizeof(GroupDesc));
+    put(o_items, p.items.data(), p.items.size() * sizeof(WorkItem));
+    put(o_lanes, p.lanes.data(), p.lanes.size() * sizeof(LaneDesc));
+    put(o_prefix, prefix.data(), prefix.size() * sizeof(uint64_t));
+    put(o_tiles, p.tiles.data(), p.tiles.size() * sizeof(TileItem));
+    put(o_launch, p.launch.data(), p.launch.size() * sizeof(uint32_t));
+    put(o_xcd, p.xcd_start.data(), p.xcd_start.size() * sizeof(uint32_t));
+    put(o_combines, p.combines.data(), p.combines.size() * sizeof(CombineItem));
+    put(o_segs, p.segs.data(), p.segs.size() * sizeof(SegDesc));
+    put(o_lgs, p.lg_seg.data(), p.lg_seg.size() * sizeof(uint32_t));
     return LBL_OK;
 }
 
@@ -369,16 +458,24 @@ lbl_status enqueue_batch(const BatchPlan &p, const BatchBuffers &b, hipStream_t 
     LBL_REQUIRE(p.finalized && b.base != nullptr, "batch enqueued before it was bound");
     const uint64_t pack_blocks = std::max<uint64_t>(1, std::min<uint64_t>((p.pack_units + 3) / 4, 1u << 16));
     if (p.sparse) {
-        hipLaunchKernelGGL(k_pack_batch<true>, dim3((unsigned)pack_blocks), dim3(256), 0, s, b.d_groups,
-                           b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units);
-        LBL_HIP_TRY(hipGetLastError());
-        LBL_HIP_TRY(launch_tiles_batch(b.d_groups, b.d_tiles, (uint32_t)p.tiles.size(), s));
+        if (p.tile.persistent) {
+            // queue counters start at zero (a kernel, so graph replays are safe)
+            hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, s, b.d_queues, kXcds);
+            LBL_HIP_TRY(hipGetLastError());
+        }
+        LBL_HIP_TRY(launch_pack_batch_tables(b.d_groups, b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units, s));
+        if (p.tile.persistent) {
+            const uint32_t n_wg = (uint32_t)std::min<uint64_t>(p.tiles.size(), (uint64_t)device_cu_count());
+            LBL_HIP_TRY(launch_tiles_batch_queue(b.d_groups, b.d_tiles, b.d_xcd_start, b.d_queues, n_wg, s));
+        } else {
+            LBL_HIP_TRY(launch_tiles_batch(b.d_groups, b.d_tiles, b.d_launch, (uint32_t)p.tiles.size(), s));
+        }
         LBL_HIP_TRY(launch_combine_batch(b.d_groups, b.d_combines, (uint32_t)p.combines.size(), s));
         return LBL_OK;
     }
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, b.d_counter);
     LBL_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_pack_batch<false>, dim3((unsigned)pack_blocks), dim3(256), 0, s, b.d_groups,
+    hipLaunchKernelGGL(k_pack_batch, dim3((unsigned)pack_blocks), dim3(256), 0, s, b.d_groups,
                        b.d_pack_prefix, (uint32_t)p.groups.size(), p.pack_units);
     LBL_HIP_TRY(hipGetLastError());
     const int wpb = p.tile.waves_per_block;
@@ -417,6 +514,7 @@ struct GraphEntry {
     uint32_t flags = 0;
     std::vector<JobRef> jobs;
     BatchPlan plan;
+    BatchTile asked;  // the tile the entry was built for (before defaults were resolved)
     BatchBuffers bufs;
     void *dmem = nullptr;
     hipGraph_t graph = nullptr;
@@ -474,9 +572,43 @@ lbl_status build_entry(GraphEntry *e)
     return LBL_OK;
 }
 
+// The cached graph for these jobs built for tile `want` (or for the tile
+// recorded for their shape class when want is null), moved to the front;
+// null if none.  Lock held.  Entries for the same jobs built for another
+// tile are released.
+GraphEntry *find_entry(const JobRef *jobs, size_t n_jobs, uint32_t flags, hipStream_t s, int device,
+                       const BatchTile *want)
+{
+    GraphEntry *hit = nullptr;
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        GraphEntry *e = it->get();
+        if (e->stream == s && e->flags == flags && e->device == device && same_jobs(e->jobs, jobs, n_jobs)) {
+            const BatchTile w = want ? *want : tuned_tile(e->plan.shape_key);
+            if (!hit && e->asked == w) {
+                hit = e;
+                g_graphs.splice(g_graphs.begin(), g_graphs, it++);
+                continue;
+            }
+            if (!want) {  // built for a tile no longer recorded for the class
+                destroy_entry(e);
+                it = g_graphs.erase(it);
+                continue;
+            }
+        }
+        ++it;
+    }
+    return hit;
+}
+
 }  // namespace
 
 BatchTile batch_tile_for(const std::string &key) { return tuned_tile(key); }
+
+std::vector<std::pair<std::string, BatchTile>> batch_tiles()
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    return std::vector<std::pair<std::string, BatchTile>>(g_tiles.begin(), g_tiles.end());
+}
 
 void batch_forget(const lbl_abs *a)
 {
@@ -504,17 +636,7 @@ lbl_status label_batch_graph(const JobRef *jobs, size_t n_jobs, uint32_t flags, 
     int cur = 0;
     LBL_HIP_TRY(hipGetDevice(&cur));
     std::lock_guard<std::mutex> lk(g_graph_mu);
-    GraphEntry *hit = nullptr;
-    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
-        GraphEntry *e = it->get();
-        if (e->stream == s && e->flags == flags && e->device == cur && same_jobs(e->jobs, jobs, n_jobs) &&
-            (!force || (e->plan.tile.unroll == force->unroll && e->plan.tile.waves_per_block == force->waves_per_block &&
-                        e->plan.tile.rows_per_item == force->rows_per_item))) {
-            g_graphs.splice(g_graphs.begin(), g_graphs, it);
-            hit = e;
-            break;
-        }
-    }
+    GraphEntry *hit = find_entry(jobs, n_jobs, flags, s, cur, force);
     if (!hit) {
         std::unique_ptr<GraphEntry> e(new GraphEntry());
         e->stream = s;
@@ -523,7 +645,8 @@ lbl_status label_batch_graph(const JobRef *jobs, size_t n_jobs, uint32_t flags, 
         e->jobs.assign(jobs, jobs + n_jobs);
         lbl_status st = plan_batch(jobs, n_jobs, cur, &e->plan);
         if (st != LBL_OK) return st;
-        plan_finalize(e->plan, force ? *force : tuned_tile(e->plan.shape_key));
+        e->asked = force ? *force : tuned_tile(e->plan.shape_key);
+        plan_finalize(e->plan, e->asked);
         st = build_entry(e.get());
         if (st != LBL_OK) {
             destroy_entry(e.get());
@@ -570,32 +693,85 @@ lbl_status lbl_tune_batch(const lbl_job *jobs, size_t n_jobs, void *hip_stream)
     LBL_HIP_TRY(hipGetDevice(&cur));
     lbl_status st = plan_batch(refs.data(), n_jobs, cur, &probe);
     if (st != LBL_OK) return st;
+    // the candidates: for sparse plans every tiling of the layout, launched
+    // persistent or one workgroup per tile; for bitpacked plans the
+    // persistent kernel's loads in flight, workgroup size and rows per item
+    std::vector<BatchTile> cands;
+    if (probe.sparse) {
+        for (int t = 1; t <= kBatchTilings + 1; ++t)
+            for (int pers : {1, 0}) {
+                BatchTile b;
+                b.tiling = t;
+                b.persistent = pers;
+                cands.push_back(b);
+            }
+    } else {
+        for (int u : {4, 8})
+            for (int w : {4, 8, 16})
+                for (int r : {32, 128, 512}) cands.push_back(BatchTile{u, w, r, 0, 1});
+    }
     hipEvent_t e0, e1;
     LBL_HIP_TRY(hipEventCreate(&e0));
     LBL_HIP_TRY(hipEventCreate(&e1));
     BatchTile best;
     float best_ms = 1e30f;
-    for (int u : {4, 8})
-        for (int w : {4, 8, 16})
-            for (int r : {32, 128, 512}) {
-                BatchTile t{u, w, r};
-                st = label_batch_graph(refs.data(), n_jobs, 0, s, &t);  // build + warm-up
-                if (st != LBL_OK) break;
-                LBL_HIP_TRY(hipEventRecord(e0, s));
-                for (int k = 0; k < 3; ++k) label_batch_graph(refs.data(), n_jobs, 0, s, &t);
-                LBL_HIP_TRY(hipEventRecord(e1, s));
-                LBL_HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                LBL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
-                }
-            }
+    for (const BatchTile &t : cands) {
+        st = label_batch_graph(refs.data(), n_jobs, 0, s, &t);  // build + warm-up
+        if (st != LBL_OK) break;
+        LBL_HIP_TRY(hipEventRecord(e0, s));
+        for (int k = 0; k < 3 && st == LBL_OK; ++k) st = label_batch_graph(refs.data(), n_jobs, 0, s, &t);
+        LBL_HIP_TRY(hipEventRecord(e1, s));
+        LBL_HIP_TRY(hipEventSynchronize(e1));
+        if (st != LBL_OK) break;
+        float ms = 0.f;
+        LBL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != LBL_OK) return st;
     set_batch_tile(probe.shape_key, best);
+    // release the candidates' graphs except the winner's, which the next
+    // lbl_label_batch of these jobs replays
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    (void)find_entry(refs.data(), n_jobs, 0, s, cur, nullptr);
+    return LBL_OK;
+}
+
+lbl_status lbl_tune_batch_describe(const lbl_job *jobs, size_t n_jobs, void *hip_stream, char *buf, size_t buf_len)
+{
+    clear_error();
+    LBL_REQUIRE(jobs != nullptr && n_jobs > 0, "no jobs");
+    LBL_REQUIRE(buf != nullptr && buf_len > 0, "null buffer");
+    std::vector<JobRef> refs(n_jobs);
+    for (size_t j = 0; j < n_jobs; ++j) refs[j] = JobRef{jobs[j].a, jobs[j].O, jobs[j].n_props, jobs[j].L};
+    int cur = 0;
+    LBL_HIP_TRY(hipGetDevice(&cur));
+    BatchPlan p;
+    lbl_status st = plan_batch(refs.data(), n_jobs, cur, &p);
+    if (st != LBL_OK) return st;
+    std::string out;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+        GraphEntry *e = nullptr;
+        for (auto &x : g_graphs)
+            if (x->stream == s && x->device == cur && same_jobs(x->jobs, refs.data(), n_jobs) &&
+                x->asked == tuned_tile(x->plan.shape_key)) {
+                e = x.get();
+                break;
+            }
+        if (e) {
+            out = p.shape_key + " -> " + batch_tile_name(e->plan) + " cached";
+        } else {
+            plan_finalize(p, tuned_tile(p.shape_key));
+            out = p.shape_key + " -> " + batch_tile_name(p) + " not built";
+        }
+    }
+    snprintf(buf, buf_len, "%s", out.c_str());
     return LBL_OK;
 }
 

@@ -63,6 +63,16 @@ struct SpTiling {
     uint32_t *block_tile = nullptr; // device [n_tiles] launch order of a one-frame launch
     SpTask *tasks_launch = nullptr; // device [n_tiles * kTileWaves] the tasks of workgroup b at b * kTileWaves
     std::vector<uint32_t> rb_tile_host;
+    // Compact partial labels (the one-frame tiling): a tile writes the
+    // partials of only the rows it touches, slots tile_slot[tile] ..
+    // tile_slot[tile + 1] holding local rows slot_row[..] (ascending); row t's
+    // partials are the slots row_slots[row_slot_off[t] .. row_slot_off[t + 1]).
+    // Null when not built (then a tile writes all kRowBlock rows).
+    uint64_t n_slots = 0;
+    uint32_t *tile_slot = nullptr;     // device [n_tiles + 1]
+    uint16_t *slot_row = nullptr;      // device [n_slots]
+    uint32_t *row_slot_off = nullptr;  // device [n_traj + 1]
+    uint32_t *row_slots = nullptr;     // device [n_slots]
 };
 
 // XCDs of an MI355X.  Workgroup b of a launch runs on XCD b % kXcds, and
@@ -119,7 +129,9 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts);
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t = 0);
 
 // Pack O, label through the tiled layout, write L (device pointers).
-lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s);
+// spans: record profiling events around the kernels (when profiling is on).
+lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s,
+                   bool spans = true);
 
 // Relative work of wavefront w of a tile workgroup (tasks are sized to it).
 double wave_share(uint32_t w);
@@ -142,6 +154,16 @@ struct TilingHost {
 };
 void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint32_t> &seg_word,
                  const std::vector<uint64_t> &rb_seg, const std::vector<uint32_t> &tiles_rb, TilingHost *out);
+// Compact partial slots of a tiling (host): row[e] is the local row of entry
+// e; tile i of block rb covers entries [tasks[i * kTileWaves].lo, the next
+// tile's first entry or the block's end).  Fails (false) if the slots
+// number 2^32 or more.
+struct CompactHost {
+    std::vector<uint32_t> tile_slot, row_slot_off, row_slots;
+    std::vector<uint16_t> slot_row;
+};
+bool make_compact(const TilingHost &h, const std::vector<uint16_t> &row, const std::vector<uint64_t> &seg_start,
+                  const std::vector<uint64_t> &rb_seg, uint64_t n_traj, CompactHost *out);
 // Cost of walking each row block's entries in rounds.
 std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg);
 // Tiles per row block (at least one each) for `target` tiles in total of

@@ -239,7 +239,8 @@ template <int WAVES>
 __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, const SpRound *__restrict__ rounds,
                                           const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
                                           const uint64_t *__restrict__ Tg, uint64_t tg_stride,
-                                          uint64_t *__restrict__ Pt, uint64_t *lds)
+                                          uint64_t *__restrict__ Pt, uint64_t *lds,
+                                          const uint16_t *__restrict__ slot_row = nullptr, uint32_t n_slot = 0)
 {
     const uint32_t lane = threadIdx.x & 63;
     // uniform across the wavefront: task fields and round records become
@@ -380,6 +381,12 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
     }
     __syncthreads();
     // streaming stores: the partials are read once, by the combine kernel
+    if (slot_row) {
+        // only the rows this tile touches, in its slots
+        for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES)
+            __builtin_nontemporal_store(acc[slot_row[k]], Pt + k);
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES) {
         const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(acc)[i];
         __builtin_nontemporal_store(v.x, Pt + 2 * i);
@@ -394,25 +401,146 @@ template <int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks_launch,
               const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg, uint64_t *__restrict__ P)
+              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg, uint64_t *__restrict__ P,
+              const uint32_t *__restrict__ tile_slot, const uint16_t *__restrict__ slot_row)
 {
     extern __shared__ uint64_t lds[];
-    tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256,
-                     P + (uint64_t)block_tile[blockIdx.x] * kRowBlock, lds);
+    const uint32_t tile = block_tile[blockIdx.x];
+    if (tile_slot) {
+        const uint32_t s0 = tile_slot[tile], s1 = tile_slot[tile + 1];
+        tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256, P + s0, lds,
+                         slot_row + s0, s1 - s0);
+    } else {
+        tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256,
+                         P + (uint64_t)tile * kRowBlock, lds);
+    }
 }
 
-// One workgroup per (pass, tile, lane group) of a batch.  The pass's nibble
-// tables are [w][G64][256], its partials [G64][n_tiles][kRowBlock].
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES)
-k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items)
+// OR of row t's compact partials: slots row_slots[row_slot_off[t] ..
+// row_slot_off[t + 1]), four loads in flight (indices past the last slot read
+// it again, which leaves the OR unchanged; a row no tile touches has none).
+__device__ __forceinline__ uint64_t row_slots_or(const uint64_t *__restrict__ P, const uint32_t *__restrict__ off,
+                                                 const uint32_t *__restrict__ slots, uint64_t t)
 {
-    extern __shared__ uint64_t lds[];
-    const TileItem it = items[blockIdx.x];
+    const uint32_t k0 = off[t], k1 = off[t + 1];
+    uint64_t bits = 0;
+    for (uint32_t kb = k0; kb < k1; kb += 4) {
+        uint64_t v[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) v[j] = P[slots[min(kb + j, k1 - 1)]];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) bits |= v[j];
+    }
+    return bits;
+}
+
+// One tile item of a batch: pass it.group, tile it.tile, lane group it.gi.
+// The pass's nibble tables are [w][G64][256], its partials
+// [G64][n_tiles][kRowBlock].
+template <int WAVES>
+__device__ __forceinline__ void batch_tile(const GroupDesc *__restrict__ groups, const TileItem &it, uint64_t *lds)
+{
     const GroupDesc &g = groups[it.group];
     tile_body<WAVES>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
                      g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256,
                      g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
+}
+
+// One workgroup per tile item: workgroup b runs items[launch[b]].
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+k_label_tiles_batch(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items,
+                    const uint32_t *__restrict__ launch)
+{
+    extern __shared__ uint64_t lds[];
+    const TileItem it = items[launch[blockIdx.x]];
+    batch_tile<WAVES>(groups, it, lds);
+}
+
+// Persistent: one workgroup per CU.  Items are split into kXcds queues
+// (queue x = items[xcd_start[x] .. xcd_start[x + 1])) so that the items
+// reading the same nibble tables run on one XCD; workgroup b starts on queue
+// b % kXcds (the XCD it runs on) and, once that queue is empty, takes items
+// from the others.  Every workgroup leaves when every queue is empty; no
+// workgroup waits for another.
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+k_label_tiles_queue(const GroupDesc *__restrict__ groups, const TileItem *__restrict__ items,
+                    const uint32_t *__restrict__ xcd_start, uint32_t *queues)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t s_item;
+    const uint32_t home = blockIdx.x % kXcds;
+    uint32_t k = 0;
+    while (k < kXcds) {
+        const uint32_t q = (home + k) % kXcds;
+        // the previous item's write-back of the accumulators is complete
+        // before the next item clears them
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t i = xcd_start[q] + atomicAdd(queues + q, 1u);
+            s_item = i < xcd_start[q + 1] ? i : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        const uint32_t i = s_item;
+        if (i == 0xFFFFFFFFu) {
+            ++k;  // uniform: this queue is empty, try the next
+            continue;
+        }
+        const TileItem it = items[i];
+        batch_tile<WAVES>(groups, it, lds);
+    }
+}
+
+// Bit p set iff byte p of src[0 .. n) is non-zero, 1 <= n <= 64, any
+// alignment: the 4-byte-aligned words holding those bytes are loaded (each
+// holds at least one byte of the range, so no load leaves the caller's
+// buffer's pages) and bytes outside the range are dropped.
+__device__ __forceinline__ uint64_t byte_mask_any(const uint8_t *src, uint32_t n)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src);
+    const uint32_t mis = (uint32_t)(a & 3u);
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(a - mis);
+    const uint32_t nd = (mis + n + 3) >> 2;  // this lane's words: 1 .. 17
+    const uint32_t kmax = (n + 6) >> 2;      // an upper bound of nd for every lane
+    uint64_t lo = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k)
+        if (k < kmax) {
+            const uint32_t v = k < nd ? p[k] : 0u;
+            lo |= (uint64_t)nz_bytes(v) << (4 * k);
+        }
+    const uint32_t hi = (kmax > 16 && nd > 16) ? nz_bytes(p[16]) : 0u;
+    const uint64_t m = mis ? (lo >> mis) | ((uint64_t)hi << (64 - mis)) : lo;
+    return n >= 64 ? m : m & ((1ull << n) - 1ull);
+}
+
+// One wavefront per (pass, word, lane group): lane b holds cell b of the
+// word; for every job of the lane group it reads the cell's n_props bytes of
+// that job's O (contiguous) into the job's columns of the cell's mask, then
+// the word's nibble tables for the lane group are written.
+__global__ void __launch_bounds__(256)
+k_pack_batch_tables(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
+                    uint64_t n_units)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t u = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         u < n_units; u += waves) {
+        uint32_t gidx = 0;
+        while (gidx + 1 < n_groups && prefix[gidx + 1] <= u) ++gidx;
+        const GroupDesc &g = groups[gidx];
+        const uint64_t local = u - prefix[gidx];
+        const uint32_t G = g.G64;
+        const uint32_t w = (uint32_t)(local / G), gi = (uint32_t)(local % G);
+        const uint64_t cell = g.word_cell[(uint64_t)w * 64 + lane];
+        uint64_t m = 0;
+        for (uint32_t sgi = g.lg_seg[gi], s1 = g.lg_seg[gi + 1]; sgi < s1; ++sgi) {
+            const SegDesc d = g.segs[sgi];
+            m |= byte_mask_any(d.O + cell * d.n_props, d.n_props) << d.bit;
+        }
+        write_tables(m, g.Ow + ((uint64_t)w * G + gi) * 256, lane);
+    }
 }
 
 // OR of row t's partials over the tiles of its row block.
@@ -434,79 +562,125 @@ __device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P,
     return bits;
 }
 
-// One wavefront per (pass, lane group, rows [row0, row1)): lane l holds the
-// descriptor of column (gi, l); 64 rows at a time, lane j ORs the partials
-// of row t0 + j, then every row's bits are broadcast and each lane writes its
-// column's byte into its job's L.
+// The label bytes of rows [t0, t0 + n) of one job (n <= 64), written as one
+// contiguous block L[t0 * np .. (t0 + n) * np): lane r holds the job's bits
+// of row t0 + r in v (bit p = proposition p).  The block is staged in LDS at
+// its offset modulo 16 (each lane ORs its row's bytes into 4-byte-aligned
+// words; neighbouring rows share the words at their boundary), then written
+// with 16-byte stores; the units at the block's two ends, which also hold
+// bytes of other rows, are written byte by byte, so no byte outside the
+// block is stored.  stage: 64 * 64 + 32 bytes of this wavefront's LDS (the
+// last row's words reach at most 2 bytes past the block).
+__device__ __forceinline__ void emit_block(uint32_t *stage, uint32_t lane, uint32_t n, uint64_t v, uint8_t *dst,
+                                           uint32_t np)
+{
+    const uintptr_t base = reinterpret_cast<uintptr_t>(dst);
+    const uint32_t mis = (uint32_t)(base & 15u);
+    const uint32_t total = mis + n * np;  // staged bytes, <= 15 + 4096
+    const uint32_t n_units = (total + 15) >> 4;
+    uint4 *st4 = reinterpret_cast<uint4 *>(stage);
+    for (uint32_t u = lane; u < n_units; u += 64) st4[u] = make_uint4(0u, 0u, 0u, 0u);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const uint32_t o = mis + lane * np;
+        const uint32_t sh = 8 * (o & 3u);
+        uint32_t *w = stage + (o >> 2);
+        const uint32_t nq = ((o & 3u) + np + 3) >> 2;
+        uint32_t prev = 0;
+        for (uint32_t q = 0; q < nq; ++q) {
+            const uint32_t cur = 4 * q < np ? spread_nib((uint32_t)(v >> (4 * q)) & 0xFu) : 0u;
+            const uint32_t out = sh ? (cur << sh) | (prev >> (32 - sh)) : cur;
+            __hip_atomic_fetch_or(w + q, out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            prev = cur;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint8_t *g = dst - mis;
+    for (uint32_t u = lane; u < n_units; u += 64) {
+        const uint4 x = st4[u];
+        const uint32_t lo = 16 * u, hi = lo + 16;
+        if (lo >= mis && hi <= total) {
+            *reinterpret_cast<uint4 *>(g + lo) = x;
+        } else {
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            for (uint32_t b = 0; b < 16; ++b)
+                if (lo + b >= mis && lo + b < total) g[lo + b] = (uint8_t)(xs[b >> 2] >> (8 * (b & 3u)));
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the stage is reused by the next block
+}
+
+// One wavefront per (pass, lane group, rows [row0, row1)), 64 rows at a
+// time: lane j ORs the partials of row t0 + j (the 64 columns of the lane
+// group), then every job of the lane group gets its block of label bytes for
+// those rows (emit_block).  Each byte of L belongs to one job, one row range
+// and one lane group, so exactly one wavefront writes it.
 __global__ void __launch_bounds__(64)
 k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restrict__ items)
 {
+    // 64 rows of at most 64 bytes at an offset below 16, plus the word a
+    // row's last bytes may spill into
+    __shared__ uint32_t stage[(64 * 64 + 32) / 4];
     const uint32_t lane = threadIdx.x;
     const CombineItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    const LaneDesc d = g.lanes[it.gi * 64 + lane];
     const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_tiles * kRowBlock;
+    const uint32_t s0 = g.lg_seg[it.gi], s1 = g.lg_seg[it.gi + 1];
     for (uint64_t t0 = it.row0; t0 < it.row1; t0 += 64) {
         const uint64_t t = t0 + lane;
         const uint64_t bits = t < it.row1 ? row_partials(Pg, g.sp_rb_tile, t) : 0ull;
         const uint32_t n = (uint32_t)min<uint64_t>(64, it.row1 - t0);
-        for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)bits, j);
-            const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), j);
-            const uint64_t b = ((uint64_t)hi << 32) | lo;
-            if (d.L) d.L[(t0 + j) * d.n_props] = (uint8_t)((b >> lane) & 1ull);
+        for (uint32_t sgi = s0; sgi < s1; ++sgi) {
+            const SegDesc d = g.segs[sgi];
+            const uint64_t v = d.n_props >= 64 ? bits : (bits >> d.bit) & ((1ull << d.n_props) - 1ull);
+            emit_block(stage, lane, n, v, d.L + t0 * d.n_props, d.n_props);
         }
     }
 }
 
-// Rows' label bytes from their partials.  When n_props is a multiple of 16
-// (and L 16-byte aligned) one wavefront takes 64 consecutive rows: lane j ORs
-// the partials of row t0 + j (coalesced over rows), then the rows' bytes are
-// written as consecutive 16-byte units, lane l writing units l, l + 64, ...
-// of the block's n_props * 64 bytes, fetching the bits of each unit's row
-// from the lane that holds them.  Otherwise one thread per row, 4-byte or
-// single-byte stores.
+// Rows' label bytes from their partials.  One wavefront takes 64 consecutive
+// rows: lane j ORs the partials of row t0 + j (its compact slots when the
+// tiling has them, else the row's entry in every tile of its row block).
+// When n_props is a multiple of 16 (and L 16-byte aligned) the rows' bytes
+// are written as consecutive 16-byte units, lane l writing units l, l + 64,
+// ... of the block's n_props * 64 bytes, fetching the bits of each unit's row
+// from the lane that holds them; otherwise the block is staged in LDS and
+// written by emit_block.
 __global__ void __launch_bounds__(256)
-k_combine(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile, uint64_t n_traj, uint32_t n_props,
-          uint8_t *__restrict__ L)
+k_combine(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile,
+          const uint32_t *__restrict__ row_slot_off, const uint32_t *__restrict__ row_slots, uint64_t n_traj,
+          uint32_t n_props, uint8_t *__restrict__ L)
 {
+    __shared__ uint32_t stage[4][(64 * 64 + 32) / 4];
     const bool v16 = (n_props & 15u) == 0 && (reinterpret_cast<uintptr_t>(L) & 15u) == 0;
-    if (v16) {
-        const uint32_t lane = threadIdx.x & 63;
-        const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-        const uint64_t n_groups = (n_traj + 63) / 64;
-        const uint32_t upr = n_props / 16;  // 16-byte units per row: 1 .. 4
-        const uint32_t shift = upr == 1 ? 0 : upr == 2 ? 1 : upr == 4 ? 2 : 32;  // 32: not a power of two
-        for (uint64_t grp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; grp < n_groups; grp += n_waves) {
-            const uint64_t t0 = grp * 64, t = t0 + lane;
-            const uint64_t bits = t < n_traj ? row_partials(P, rb_tile, t) : 0ull;
-            const uint32_t units = (uint32_t)min<uint64_t>(64, n_traj - t0) * upr;
-            uint4 *dst = reinterpret_cast<uint4 *>(L + t0 * n_props);
-            // uniform trip count: every lane takes part in the shuffles
-            for (uint32_t ub = 0; ub < units; ub += 64) {
-                const uint32_t u = ub + lane;  // < 64 * upr, so row < 64
-                const uint32_t row = min(shift < 32 ? u >> shift : u / upr, 63u);
-                const uint32_t c = u - row * upr;
-                const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)bits, (int)row);
-                const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(bits >> 32), (int)row);
-                const uint32_t b = (uint32_t)((((uint64_t)hi << 32) | lo) >> (16 * c)) & 0xFFFFu;
-                if (u < units)
-                    dst[u] = make_uint4(spread_nib(b & 0xFu), spread_nib((b >> 4) & 0xFu), spread_nib((b >> 8) & 0xFu),
-                                        spread_nib(b >> 12));
-            }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t n_groups = (n_traj + 63) / 64;
+    const uint32_t upr = n_props / 16;  // 16-byte units per row: 1 .. 4
+    const uint32_t shift = upr == 1 ? 0 : upr == 2 ? 1 : upr == 4 ? 2 : 32;  // 32: not a power of two
+    for (uint64_t grp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; grp < n_groups; grp += n_waves) {
+        const uint64_t t0 = grp * 64, t = t0 + lane;
+        uint64_t bits = 0;
+        if (t < n_traj)
+            bits = row_slot_off ? row_slots_or(P, row_slot_off, row_slots, t) : row_partials(P, rb_tile, t);
+        const uint32_t n = (uint32_t)min<uint64_t>(64, n_traj - t0);
+        if (!v16) {
+            emit_block(stage[wave], lane, n, bits, L + t0 * n_props, n_props);
+            continue;
         }
-        return;
-    }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const bool v4 = (n_props & 3u) == 0 && (reinterpret_cast<uintptr_t>(L) & 3u) == 0;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_traj; t += stride) {
-        const uint64_t bits = row_partials(P, rb_tile, t);
-        uint8_t *dst = L + t * n_props;
-        if (v4) {
-            for (uint32_t p = 0; p < n_props; p += 4)
-                *reinterpret_cast<uint32_t *>(dst + p) = spread_nib((uint32_t)(bits >> p) & 0xFu);
-        } else {
-            for (uint32_t p = 0; p < n_props; ++p) dst[p] = (uint8_t)((bits >> p) & 1ull);
+        const uint32_t units = n * upr;
+        uint4 *dst = reinterpret_cast<uint4 *>(L + t0 * n_props);
+        // uniform trip count: every lane takes part in the shuffles
+        for (uint32_t ub = 0; ub < units; ub += 64) {
+            const uint32_t u = ub + lane;  // < 64 * upr, so row < 64
+            const uint32_t row = min(shift < 32 ? u >> shift : u / upr, 63u);
+            const uint32_t c = u - row * upr;
+            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)bits, (int)row);
+            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(bits >> 32), (int)row);
+            const uint32_t b = (uint32_t)((((uint64_t)hi << 32) | lo) >> (16 * c)) & 0xFFFFu;
+            if (u < units)
+                dst[u] = make_uint4(spread_nib(b & 0xFu), spread_nib((b >> 4) & 0xFu), spread_nib((b >> 8) & 0xFu),
+                                    spread_nib(b >> 12));
         }
     }
 }
@@ -745,6 +919,47 @@ void make_tiling(const std::vector<uint64_t> &seg_start, const std::vector<uint3
         for (uint32_t b = g; b < n_tiles; b += kXcds) out->block_tile[b] = key[rank++].second;
 }
 
+bool make_compact(const TilingHost &h, const std::vector<uint16_t> &row, const std::vector<uint64_t> &seg_start,
+                  const std::vector<uint64_t> &rb_seg, uint64_t n_traj, CompactHost *out)
+{
+    const size_t n_rb = rb_seg.size() - 1;
+    const uint32_t n_tiles = (uint32_t)(h.tasks.size() / kTileWaves);
+    out->tile_slot.assign(n_tiles + 1, 0);
+    out->slot_row.clear();
+    std::vector<uint32_t> row_cnt(n_traj + 1, 0);
+    std::vector<uint64_t> bm(kRowBlock / 64);
+    uint64_t n_slots = 0;
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        const uint64_t E1 = seg_start[rb_seg[rb + 1]];
+        for (uint32_t i = h.rb_tile[rb]; i < h.rb_tile[rb + 1]; ++i) {
+            const uint64_t lo = h.tasks[(size_t)i * kTileWaves].lo;
+            const uint64_t hi = i + 1 < h.rb_tile[rb + 1] ? h.tasks[(size_t)(i + 1) * kTileWaves].lo : E1;
+            std::fill(bm.begin(), bm.end(), 0ull);
+            for (uint64_t e = lo; e < hi; ++e) bm[row[e] >> 6] |= 1ull << (row[e] & 63u);
+            for (uint32_t q = 0; q < bm.size(); ++q)
+                for (uint64_t m = bm[q]; m; m &= m - 1) {
+                    const uint32_t r = q * 64 + (uint32_t)__builtin_ctzll(m);
+                    out->slot_row.push_back((uint16_t)r);
+                    ++row_cnt[rb * kRowBlock + r];
+                }
+            n_slots = out->slot_row.size();
+            if (n_slots >= (1ull << 32)) return false;
+            out->tile_slot[i + 1] = (uint32_t)n_slots;
+        }
+    }
+    // a tile's slots are row-ascending, so filling row lists tile by tile
+    // leaves each row's slots in tile order
+    out->row_slot_off.assign(n_traj + 1, 0);
+    for (uint64_t t = 0; t < n_traj; ++t) out->row_slot_off[t + 1] = out->row_slot_off[t] + row_cnt[t];
+    out->row_slots.assign(n_slots, 0);
+    std::vector<uint32_t> fill(out->row_slot_off.begin(), out->row_slot_off.end() - 1);
+    for (size_t rb = 0; rb < n_rb; ++rb)
+        for (uint32_t i = h.rb_tile[rb]; i < h.rb_tile[rb + 1]; ++i)
+            for (uint32_t k = out->tile_slot[i]; k < out->tile_slot[i + 1]; ++k)
+                out->row_slots[fill[rb * kRowBlock + out->slot_row[k]]++] = k;
+    return true;
+}
+
 SparseLayout::~SparseLayout()
 {
     (void)hipFree(row);
@@ -756,16 +971,40 @@ SparseLayout::~SparseLayout()
         (void)hipFree(t.rb_tile);
         (void)hipFree(t.block_tile);
         (void)hipFree(t.tasks_launch);
+        (void)hipFree(t.tile_slot);
+        (void)hipFree(t.slot_row);
+        (void)hipFree(t.row_slot_off);
+        (void)hipFree(t.row_slots);
     }
 }
 
 void free_sparse(SparseLayout *sp) { delete sp; }
 
-hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, uint32_t n_tiles, hipStream_t s)
+hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const uint64_t *d_prefix, uint32_t n_groups,
+                                    uint64_t n_units, hipStream_t s)
+{
+    if (n_units == 0) return hipSuccess;
+    const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((n_units + 3) / 4, 1u << 16));
+    hipLaunchKernelGGL(k_pack_batch_tables, dim3((unsigned)blocks), dim3(256), 0, s, d_groups, d_prefix, n_groups,
+                       n_units);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, const uint32_t *d_launch,
+                              uint32_t n_tiles, hipStream_t s)
 {
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_label_tiles_batch<kTileWaves>, dim3(n_tiles), dim3(64 * kTileWaves), kTileLds, s, d_groups,
-                       d_tiles);
+                       d_tiles, d_launch);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_batch_queue(const GroupDesc *d_groups, const TileItem *d_tiles, const uint32_t *d_xcd_start,
+                                    uint32_t *d_queues, uint32_t n_workgroups, hipStream_t s)
+{
+    if (n_workgroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_label_tiles_queue<kTileWaves>, dim3(n_workgroups), dim3(64 * kTileWaves), kTileLds, s,
+                       d_groups, d_tiles, d_xcd_start, d_queues);
     return hipGetLastError();
 }
 
@@ -774,6 +1013,22 @@ hipError_t launch_combine_batch(const GroupDesc *d_groups, const CombineItem *d_
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_combine_batch, dim3(n_items), dim3(64), 0, s, d_groups, d_items);
     return hipGetLastError();
+}
+
+static lbl_status upload_compact(const CompactHost &c, SpTiling *t, size_t *bytes)
+{
+    t->n_slots = c.slot_row.size();
+    auto up = [](void **dst, const void *src, size_t n) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(n, 1));
+        if (e == hipSuccess && n) e = hipMemcpy(*dst, src, n, hipMemcpyHostToDevice);
+        return e;
+    };
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->tile_slot), c.tile_slot.data(), c.tile_slot.size() * 4));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->slot_row), c.slot_row.data(), c.slot_row.size() * 2));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->row_slot_off), c.row_slot_off.data(), c.row_slot_off.size() * 4));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->row_slots), c.row_slots.data(), c.row_slots.size() * 4));
+    *bytes += c.tile_slot.size() * 4 + c.slot_row.size() * 2 + c.row_slot_off.size() * 4 + c.row_slots.size() * 4;
+    return LBL_OK;
 }
 
 static lbl_status upload_tiling(const TilingHost &h, SpTiling *t, size_t *bytes)
@@ -934,8 +1189,12 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
     LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles_batch<kTileWaves>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
+    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles_queue<kTileWaves>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
     const uint32_t n_cu = (uint32_t)device_cu_count();
     sp->tilings.resize(1 + kBatchTilings);
+    std::vector<uint16_t> rows_host(nnz);
+    if (nnz) LBL_HIP_TRY(hipMemcpy(rows_host.data(), sp->row, nnz * sizeof(uint16_t), hipMemcpyDeviceToHost));
     for (int i = 0; i <= kBatchTilings; ++i) {
         std::vector<uint32_t> k = i == 0 ? choose_tiles(block_costs(seg_start, rb_seg), n_cu)
                                          : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
@@ -943,6 +1202,11 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
         make_tiling(seg_start, seg_word, rb_seg, k, &h);
         lbl_status st = upload_tiling(h, &sp->tilings[i], &sp->round_bytes);
         if (st != LBL_OK) return st;
+        CompactHost c;
+        if (i == 0 && make_compact(h, rows_host, seg_start, rb_seg, a->n_traj, &c)) {
+            st = upload_compact(c, &sp->tilings[i], &sp->round_bytes);
+            if (st != LBL_OK) return st;
+        }
     }
     LBL_HIP_TRY(hipDeviceSynchronize());
     a->sp = sp.release();
@@ -960,17 +1224,24 @@ lbl_status build_sparse(lbl_abs *a)
 
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)
 {
-    return up256((size_t)a->n_words * 256 * n_lane_groups * sizeof(uint64_t)) +
-           (size_t)n_lane_groups * a->sp->tilings[t].n_tiles * kRowBlock * sizeof(uint64_t);
+    const SpTiling &tl = a->sp->tilings[t];
+    const size_t partials = tl.tile_slot && n_lane_groups == 1 ? (size_t)tl.n_slots
+                                                                : (size_t)n_lane_groups * tl.n_tiles * kRowBlock;
+    return up256((size_t)a->n_words * 256 * n_lane_groups * sizeof(uint64_t)) + partials * sizeof(uint64_t);
 }
 
-lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s)
+lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s,
+                   bool spans)
 {
     LBL_REQUIRE(a->sp != nullptr, "the abstraction has no sparse layout");
     const SparseLayout &sp = *a->sp;
     const SpTiling &tl = sp.tilings[0];
     uint64_t *Tg = static_cast<uint64_t *>(ws);
     uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
+    auto span_begin = [&](hipStream_t st) { return spans ? lbl::span_begin(st) : nullptr; };
+    auto span_end = [&](void *b, hipStream_t st, int kind) {
+        if (spans) lbl::span_end(b, st, kind);
+    };
     void *spn = span_begin(s);
     hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
                        n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
@@ -978,12 +1249,12 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     span_end(spn, s, 0);
     spn = span_begin(s);
     hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.block_tile,
-                       tl.tasks_launch, tl.rounds, sp.row, sp.val, Tg, P);
+                       tl.tasks_launch, tl.rounds, sp.row, sp.val, Tg, P, tl.tile_slot, tl.slot_row);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
     spn = span_begin(s);
-    hipLaunchKernelGGL(k_combine, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile, a->n_traj,
-                       n_props, L);
+    hipLaunchKernelGGL(k_combine, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile,
+                       tl.row_slot_off, tl.row_slots, a->n_traj, n_props, L);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 3);
     return LBL_OK;

@@ -13,6 +13,7 @@
 #include <memory>
 #include <sstream>
 
+#include "batch.h"
 #include "profile.h"
 #include "sparse.h"
 #include "tune.h"
@@ -284,6 +285,13 @@ lbl_status lbl_tune_save(const char *path)
               << ", \"us\": " << kv.second.us << "}";
             first = false;
         }
+        for (const auto &kv : batch_tiles()) {
+            const BatchTile &t = kv.second;
+            o << (first ? "" : ",\n") << "  {\"batch\": \"" << kv.first << "\", \"unroll\": " << t.unroll
+              << ", \"waves\": " << t.waves_per_block << ", \"rows\": " << t.rows_per_item
+              << ", \"tiling\": " << t.tiling << ", \"persistent\": " << t.persistent << "}";
+            first = false;
+        }
         o << "\n]\n";
     }
     std::ofstream f(path);
@@ -302,6 +310,7 @@ lbl_status lbl_tune_load(const char *path)
     ss << f.rdbuf();
     const std::string text = ss.str();
     std::map<std::string, Entry> loaded;
+    std::vector<std::pair<std::string, BatchTile>> batch_loaded;
     size_t pos = 0;
     while ((pos = text.find('{', pos)) != std::string::npos) {
         const size_t end = text.find('}', pos);
@@ -326,6 +335,21 @@ lbl_status lbl_tune_load(const char *path)
         };
         std::string key, kname;
         double unroll, waves, mt, mw, us;
+        if (str_field("batch", &key)) {
+            // a batch shape class and its launch choices
+            double rows, tiling, pers;
+            LBL_REQUIRE(num_field("unroll", &unroll) && num_field("waves", &waves) && num_field("rows", &rows) &&
+                            num_field("tiling", &tiling) && num_field("persistent", &pers),
+                        "malformed tune cache batch entry");
+            BatchTile t{(int)unroll, (int)waves, (int)rows, (int)tiling, (int)pers};
+            LBL_REQUIRE((t.unroll == 4 || t.unroll == 8) && t.waves_per_block >= 1 && t.waves_per_block <= 16 &&
+                            t.rows_per_item >= 1 && t.tiling >= 0 && t.tiling <= kBatchTilings + 1 &&
+                            (t.persistent == 0 || t.persistent == 1),
+                        "tune cache batch entry has an unsupported tile");
+            batch_loaded.push_back({key, t});
+            pos = end + 1;
+            continue;
+        }
         LBL_REQUIRE(str_field("key", &key) && str_field("kernel", &kname) && num_field("unroll", &unroll) &&
                         num_field("waves", &waves) && num_field("m_tiles", &mt) && num_field("mfma_waves", &mw) &&
                         num_field("us", &us),
@@ -346,6 +370,7 @@ lbl_status lbl_tune_load(const char *path)
         loaded[key] = e;
         pos = end + 1;
     }
+    for (auto &kv : batch_loaded) set_batch_tile(kv.first, kv.second);
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &kv : loaded) g_cache[kv.first] = kv.second;
     return LBL_OK;

@@ -40,7 +40,7 @@ EXPORTS = (
     "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_batch", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
     "lbl_serve_start", "lbl_serve_submit", "lbl_serve_wait", "lbl_serve_stats_get", "lbl_serve_stop",
     "lbl_cell_position", "lbl_last_error", "lbl_version", "lbl_profile_enable", "lbl_profile_read",
-    "lbl_raster_frame", "lbl_product_shortest_paths",
+    "lbl_raster_frame", "lbl_product_shortest_paths", "lbl_tune_batch_describe",
 )
 
 
@@ -121,6 +121,7 @@ def lib():
         "lbl_tune_save": [ctypes.c_char_p],
         "lbl_tune_load": [ctypes.c_char_p],
         "lbl_tune_describe": [vp, u32, ctypes.c_char_p, ctypes.c_size_t],
+        "lbl_tune_batch_describe": [ctypes.POINTER(Job), ctypes.c_size_t, vp, ctypes.c_char_p, ctypes.c_size_t],
         "lbl_serve_start": [ctypes.POINTER(ServeCfg), ctypes.POINTER(vp)],
         "lbl_serve_submit": [vp, vp, vp, u32, vp, ctypes.POINTER(u64)],
         "lbl_serve_wait": [vp, u64, i64],
@@ -299,6 +300,12 @@ def _jobs(jobs):
 
 def tune_batch(jobs, stream=None) -> None:
     _check(lib().lbl_tune_batch(_jobs(jobs), len(jobs), _stream(stream)))
+
+
+def tune_batch_describe(jobs, stream=None) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().lbl_tune_batch_describe(_jobs(jobs), len(jobs), _stream(stream), buf, len(buf)))
+    return buf.value.decode()
 
 
 def tune_save(path: str) -> None:

@@ -84,6 +84,34 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
         for (uint32_t c = 0; c < j.n_props; ++c) CHECK(seen[j.L + c] == 1);
     }
     CHECK(seen.size() == want);
+    // segments: every job once, whole, inside one lane group, columns
+    // disjoint and matching the lane tables
+    CHECK(inside(b.d_segs, p.segs.size() * sizeof(SegDesc)));
+    CHECK(inside(b.d_lg_seg, p.lg_seg.size() * sizeof(uint32_t)));
+    std::map<const uint8_t *, int> seg_seen;
+    for (size_t g = 0; g < p.groups.size(); ++g) {
+        CHECK(gs[g].segs == b.d_segs);
+        CHECK(inside(gs[g].lg_seg, (p.groups[g].G64 + 1) * sizeof(uint32_t)));
+        const uint32_t *lgs = p.lg_seg.data() + p.lgs_off[g];
+        for (uint32_t gi = 0; gi < p.groups[g].G64; ++gi) {
+            CHECK(lgs[gi] <= lgs[gi + 1] && lgs[gi + 1] <= p.segs.size());
+            uint64_t cols = 0;
+            for (uint32_t sgi = lgs[gi]; sgi < lgs[gi + 1]; ++sgi) {
+                const SegDesc &d = p.segs[sgi];
+                CHECK(d.n_props >= 1 && d.bit + d.n_props <= 64);
+                const uint64_t m = (d.n_props == 64 ? ~0ull : ((1ull << d.n_props) - 1)) << d.bit;
+                CHECK((cols & m) == 0);
+                cols |= m;
+                seg_seen[d.L]++;
+                for (uint32_t c = 0; c < d.n_props; ++c) {
+                    const LaneDesc &ld = p.lanes[p.lane_off[g] + gi * 64 + d.bit + c];
+                    CHECK(ld.L == d.L + c && ld.O == d.O + c && ld.n_props == d.n_props);
+                }
+            }
+        }
+    }
+    CHECK(seg_seen.size() == jobs.size());
+    for (auto &kv : seg_seen) CHECK(kv.second == 1);
     uint64_t pairs = 0;
     for (const JobRef &j : jobs) pairs += j.a->n_traj * j.n_props;
     CHECK(p.pairs == pairs);
@@ -93,7 +121,8 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     for (const JobRef &j : jobs) sparse = sparse && j.a->sp != nullptr;
     CHECK(p.sparse == sparse);
     if (!p.sparse) return;
-    CHECK(p.tiling >= 1 && p.tiling <= kBatchTilings);
+    CHECK(p.tiling >= 0 && p.tiling <= kBatchTilings);
+    CHECK(tile.tiling == 0 ? p.tiling == p.default_tiling : p.tiling == tile.tiling - 1);
     std::vector<std::pair<const uint8_t *, const uint8_t *>> p_ranges;
     std::set<std::tuple<uint32_t, uint32_t, uint32_t>> tiles;
     uint64_t want_tiles = 0;
@@ -121,6 +150,33 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
         tiles.insert(std::make_tuple(t.group, t.tile, t.gi));
     }
     CHECK(tiles.size() == p.tiles.size() && p.tiles.size() == want_tiles);
+    // per-XCD queues partition the tiles; the one-per-tile launch order is a
+    // permutation of them
+    CHECK(p.xcd_start.size() == kXcds + 1 && p.xcd_start.front() == 0 && p.xcd_start.back() == p.tiles.size());
+    for (uint32_t x = 0; x < kXcds; ++x) CHECK(p.xcd_start[x] <= p.xcd_start[x + 1]);
+    CHECK(inside(b.d_xcd_start, p.xcd_start.size() * sizeof(uint32_t)));
+    CHECK(inside(b.d_queues, kXcds * sizeof(uint32_t)));
+    CHECK(reinterpret_cast<uint8_t *>(b.d_queues) == reinterpret_cast<uint8_t *>(b.d_counter) + 4);
+    CHECK(inside(b.d_launch, p.launch.size() * sizeof(uint32_t)));
+    {
+        std::vector<uint32_t> perm = p.launch;
+        std::sort(perm.begin(), perm.end());
+        CHECK(perm.size() == p.tiles.size());
+        for (size_t i = 0; i < perm.size(); ++i) CHECK(perm[i] == i);
+    }
+    // tiles that share a table set (pass, lane group, position in the row
+    // block) are on one queue
+    {
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::set<uint32_t>> where;
+        for (uint32_t x = 0; x < kXcds; ++x)
+            for (uint32_t i = p.xcd_start[x]; i < p.xcd_start[x + 1]; ++i) {
+                const TileItem &t = p.tiles[i];
+                const auto &rbt = p.group_abs[t.group]->sp->tilings[p.tiling].rb_tile_host;
+                const uint32_t rb = (uint32_t)(std::upper_bound(rbt.begin(), rbt.end(), t.tile) - rbt.begin() - 1);
+                where[std::make_tuple(t.group, t.gi, t.tile - rbt[rb])].insert(x);
+            }
+        for (auto &kv : where) CHECK(kv.second.size() == 1);
+    }
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> rows;
     for (const CombineItem &c : p.combines) {
         CHECK(c.group < p.groups.size() && c.gi < p.groups[c.group].G64);
@@ -132,6 +188,33 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
             const uint64_t covered_rows = rows[std::make_pair((uint32_t)g, gi)];
             CHECK(covered_rows == p.groups[g].n_traj);
         }
+    // label bytes: every combine item writes, for each job of its lane group,
+    // the contiguous block of its rows' bytes; across all items each job's
+    // L is covered exactly once (no byte, hence no store unit inside a
+    // block, is written by two wavefronts)
+    std::map<const uint8_t *, std::vector<std::pair<uint64_t, uint64_t>>> blocks;
+    std::map<const uint8_t *, uint64_t> job_bytes;
+    for (const JobRef &j : jobs) job_bytes[j.L] = j.a->n_traj * j.n_props;
+    for (const CombineItem &c : p.combines) {
+        const uint32_t *lgs = p.lg_seg.data() + p.lgs_off[c.group];
+        for (uint64_t t0 = c.row0; t0 < c.row1; t0 += 64) {
+            const uint64_t n = std::min<uint64_t>(64, c.row1 - t0);
+            for (uint32_t sgi = lgs[c.gi]; sgi < lgs[c.gi + 1]; ++sgi) {
+                const SegDesc &d = p.segs[sgi];
+                blocks[d.L].push_back({t0 * d.n_props, (t0 + n) * d.n_props});
+            }
+        }
+    }
+    CHECK(blocks.size() == job_bytes.size());
+    for (auto &kv : blocks) {
+        std::sort(kv.second.begin(), kv.second.end());
+        uint64_t at = 0;
+        for (auto &r : kv.second) {
+            CHECK(r.first == at && r.second > r.first);
+            at = r.second;
+        }
+        CHECK(at == job_bytes[kv.first]);
+    }
 }
 
 // A fake sparse layout for an abstraction of `rows` rows: tilings with
@@ -151,6 +234,14 @@ static SparseLayout *fake_layout(uint64_t rows, uint64_t base)
         t.tasks = reinterpret_cast<SpTask *>(base + 0x20000000ull + 0x1000000ull * i);
         t.rounds = reinterpret_cast<SpRound *>(base + 0x30000000ull + 0x1000000ull * i);
         t.rb_tile = reinterpret_cast<uint32_t *>(base + 0x40000000ull + 0x1000000ull * i);
+        // tiles of each row block: the one-frame tiling gives the first
+        // blocks the extra tiles, the batch tilings 2^(i-1) each
+        t.rb_tile_host.assign(sp->n_rb + 1, 0);
+        for (uint32_t rb = 0; rb < sp->n_rb; ++rb) {
+            const uint32_t k = i == 0 ? t.n_tiles / sp->n_rb + (rb < t.n_tiles % sp->n_rb ? 1u : 0u) : 1u << (i - 1);
+            t.rb_tile_host[rb + 1] = t.rb_tile_host[rb] + k;
+        }
+        CHECK(t.rb_tile_host[sp->n_rb] == t.n_tiles);
     }
     return sp;
 }
@@ -246,6 +337,49 @@ static void check_tiling(const std::vector<uint64_t> &start, const std::vector<u
         CHECK(next == E1);
     }
     for (uint64_t e = 0; e < nnz; ++e) CHECK(seen[e] == 1);
+    // compact partial slots: random local rows for the entries; every (row,
+    // tile) pair with an entry has exactly one slot, a tile's slots ascend,
+    // and each row's slot list names exactly its tiles' slots for that row
+    std::mt19937 rng((uint32_t)nnz);
+    const uint64_t n_traj = (uint64_t)n_rb * kRowBlock - (n_rb ? rng() % 100 : 0);
+    std::vector<uint16_t> row(nnz);
+    for (size_t rb = 0; rb < n_rb; ++rb)
+        for (uint64_t e = start[rb_seg[rb]]; e < start[rb_seg[rb + 1]]; ++e) {
+            const uint64_t lim = std::min<uint64_t>(kRowBlock, n_traj - rb * kRowBlock);
+            row[e] = (uint16_t)(rng() % lim);
+        }
+    CompactHost c;
+    CHECK(make_compact(h, row, start, rb_seg, n_traj, &c));
+    CHECK(c.tile_slot.size() == n_tiles + 1 && c.tile_slot[0] == 0 && c.tile_slot[n_tiles] == c.slot_row.size());
+    CHECK(c.row_slot_off.size() == n_traj + 1 && c.row_slot_off[n_traj] == c.slot_row.size());
+    CHECK(c.row_slots.size() == c.slot_row.size());
+    std::set<std::pair<uint64_t, uint32_t>> want_pairs, got_pairs;
+    for (size_t rb = 0; rb < n_rb; ++rb)
+        for (uint32_t t = h.rb_tile[rb]; t < h.rb_tile[rb + 1]; ++t) {
+            const uint64_t lo = h.tasks[(size_t)t * kTileWaves].lo;
+            const uint64_t hi = t + 1 < h.rb_tile[rb + 1] ? h.tasks[(size_t)(t + 1) * kTileWaves].lo
+                                                           : start[rb_seg[rb + 1]];
+            for (uint64_t e = lo; e < hi; ++e) want_pairs.insert({rb * kRowBlock + row[e], t});
+            for (uint32_t k = c.tile_slot[t]; k < c.tile_slot[t + 1]; ++k) {
+                CHECK(k == c.tile_slot[t] || c.slot_row[k] > c.slot_row[k - 1]);
+                got_pairs.insert({rb * kRowBlock + c.slot_row[k], t});
+            }
+        }
+    CHECK(got_pairs == want_pairs && got_pairs.size() == c.slot_row.size());
+    std::vector<uint32_t> slot_tile(c.slot_row.size());
+    for (uint32_t t = 0; t < n_tiles; ++t)
+        for (uint32_t k = c.tile_slot[t]; k < c.tile_slot[t + 1]; ++k) slot_tile[k] = t;
+    std::vector<uint8_t> used(c.slot_row.size(), 0);
+    for (uint64_t r = 0; r < n_traj; ++r)
+        for (uint32_t k = c.row_slot_off[r]; k < c.row_slot_off[r + 1]; ++k) {
+            const uint32_t sl = c.row_slots[k];
+            CHECK(sl < c.slot_row.size());
+            if (sl >= c.slot_row.size()) continue;
+            const size_t rb = r / kRowBlock;
+            CHECK(c.slot_row[sl] == r % kRowBlock && slot_tile[sl] >= h.rb_tile[rb] && slot_tile[sl] < h.rb_tile[rb + 1]);
+            ++used[sl];
+        }
+    for (uint8_t u : used) CHECK(u == 1);
 }
 
 static void check_tilings()
@@ -386,6 +520,13 @@ int main()
     // the same batches with the sparse layout present on every abstraction
     for (int i = 0; i < 6; ++i) abss[i].sp = fake_layout(rows[i], 0x300000000000ull + 0x100000000ull * i);
     check_case(abss, jobs, BatchTile{});
+    for (int t = 1; t <= kBatchTilings + 1; ++t)
+        for (int pers : {0, 1}) {
+            BatchTile bt;
+            bt.tiling = t;
+            bt.persistent = pers;
+            check_case(abss, jobs, bt);
+        }
     for (int trial = 0; trial < 10; ++trial) {
         std::vector<JobRef> js;
         const int n = 1 + (int)(rng() % 120);

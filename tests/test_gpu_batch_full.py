@@ -111,6 +111,55 @@ def test_full_batch_matches_oracle_then_replays_new_frames(six, jobs96):
     torch.cuda.synchronize()
 
 
+def shape_key(jobs):
+    return lbl.tune_batch_describe(jobs).split(" -> ")[0]
+
+
+@pytest.mark.parametrize("tiling", [1, 2, 3, 4, 5])
+def test_full_batch_every_launch_choice(six, jobs96, tiling, tmp_path):
+    """Each tiling of the sparse layout (the one-frame tiling, 1, 2, 4 and 8
+    tiles per row block), launched persistent and one workgroup per tile,
+    forced through the tune cache file; every job against the oracle."""
+    jobs, wants, _ = jobs96
+    key = shape_key(jobs)
+    for pers in (1, 0):
+        path = str(tmp_path / f"tune_{tiling}_{pers}.json")
+        with open(path, "w") as f:
+            f.write('[\n  {"batch": "%s", "unroll": 8, "waves": 4, "rows": 128, "tiling": %d, "persistent": %d}\n]\n'
+                    % (key, tiling, pers))
+        lbl.tune_load(path)
+        desc = lbl.tune_batch_describe(jobs)
+        assert desc.startswith(key) and f"persistent={pers}" in desc and f"tiling={tiling - 1}" in desc, desc
+        for (_, _, _, Ld) in jobs:
+            Ld.fill_(6)
+        torch.cuda.synchronize()
+        say(f"full batch, {desc}")
+        lbl.label_batch(jobs)
+        check(jobs, wants, f"tiling {tiling} persistent {pers}")
+        assert lbl.tune_batch_describe(jobs).endswith("cached")
+
+
+def test_full_batch_tuned_graph_is_replayed(six, jobs96, tmp_path):
+    """After lbl_tune_batch the cached graph for the jobs is the recorded
+    winner's, and it labels like the oracle."""
+    jobs, wants, _ = jobs96
+    say("tune the full batch")
+    lbl.tune_batch(jobs)
+    desc = lbl.tune_batch_describe(jobs)
+    say(f"tuned: {desc}")
+    assert desc.endswith("cached"), desc
+    path = str(tmp_path / "tuned.json")
+    lbl.tune_save(path)
+    text = open(path).read()
+    assert '"batch": "%s"' % shape_key(jobs) in text
+    for (_, _, _, Ld) in jobs:
+        Ld.fill_(4)
+    torch.cuda.synchronize()
+    lbl.label_batch(jobs)
+    check(jobs, wants, "tuned batch")
+    assert lbl.tune_batch_describe(jobs) == desc
+
+
 def test_full_batch_equals_one_frame_per_launch(six, jobs96):
     jobs, wants, _ = jobs96
     say("one frame per launch, sparse kernel, on the batch's jobs")
