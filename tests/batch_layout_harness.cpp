@@ -206,6 +206,27 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
         }
     }
     CHECK(blocks.size() == job_bytes.size());
+    // the store units of every block as the combine issues them: 16-byte
+    // units only where they lie inside the block, single bytes where a unit
+    // would reach past either end.  Blocks are disjoint (above), so no unit
+    // or byte is written by two wavefronts.
+    for (const auto &kv : blocks)
+        for (const auto &r : kv.second) {
+            const uintptr_t base = reinterpret_cast<uintptr_t>(kv.first) + r.first;
+            const uint64_t len = r.second - r.first, mis = base & 15u, total = mis + len;
+            uint64_t covered = 0;
+            for (uint64_t lo = 0; lo < total; lo += 16) {
+                if (lo >= mis && lo + 16 <= total) {
+                    const uintptr_t u = base - mis + lo;
+                    CHECK(u % 16 == 0 && u >= base && u + 16 <= base + len);
+                    covered += 16;
+                } else {
+                    for (uint64_t b = lo; b < lo + 16; ++b)
+                        if (b >= mis && b < total) ++covered;
+                }
+            }
+            CHECK(covered == len);
+        }
     for (auto &kv : blocks) {
         std::sort(kv.second.begin(), kv.second.end());
         uint64_t at = 0;
