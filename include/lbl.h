@@ -196,6 +196,32 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
                            uint32_t flags, void *hip_stream);
 
 /*
+ * lbl_label_frame for callers that cannot allocate device memory: code
+ * under HIP graph capture, serving loops or harnesses that forbid
+ * hipMalloc.  Same operation and result as lbl_label_frame with device
+ * pointers and LBL_KERNEL_AUTO resolved to the sparse kernel (or the
+ * bitpacked kernel for an abstraction loaded with LBL_LOAD_NO_SPARSE):
+ * O (n_cells x n_props bytes, the abstraction's cell order) and L (n_traj x
+ * n_props bytes, written 0/1) are device memory owned by the caller, and the
+ * call is asynchronous on hip_stream.
+ *
+ * The frame's intermediates (nibble tables and tile partials, or packed
+ * masks) go to one static device array of 96 MiB that each GPU the library
+ * runs on holds until the process ends; the call allocates nothing.  Every
+ * call on one GPU uses that GPU's array, so calls that overlap on one GPU
+ * (two streams, or two host threads) race: serialize them.  A call whose
+ * intermediates do not fit (grids of more than about 2^20 cells: the tables
+ * take 2 KiB per 64-cell word) fails with LBL_EINVAL and names the size it
+ * needs; lbl_label_frame serves such frames.
+ *
+ * Errors: LBL_EINVAL for a null handle or pointer, n_props outside [1, 64],
+ * the current device not being the abstraction's, or intermediates larger
+ * than the array; LBL_EDEVICE for a HIP error.
+ */
+lbl_status lbl_label_frame_noalloc(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint8_t *L,
+                                   void *hip_stream);
+
+/*
  * Label many frames, possibly against different abstractions, in one
  * persistent-kernel launch.  Each job is one frame as in lbl_label_frame
  * (device pointers; flags must be 0).  Jobs on the same abstraction share

@@ -40,7 +40,7 @@ EXPORTS = (
     "lbl_label_frame", "lbl_label_batch", "lbl_tune", "lbl_tune_batch", "lbl_tune_save", "lbl_tune_load", "lbl_tune_describe",
     "lbl_serve_start", "lbl_serve_submit", "lbl_serve_wait", "lbl_serve_stats_get", "lbl_serve_stop",
     "lbl_cell_position", "lbl_last_error", "lbl_version", "lbl_profile_enable", "lbl_profile_read",
-    "lbl_raster_frame", "lbl_product_shortest_paths", "lbl_tune_batch_describe",
+    "lbl_raster_frame", "lbl_product_shortest_paths", "lbl_tune_batch_describe", "lbl_label_frame_noalloc",
 )
 
 
@@ -115,6 +115,7 @@ def lib():
         "lbl_free_abstraction": [vp],
         "lbl_abstraction_info": [vp, ctypes.POINTER(AbsInfo)],
         "lbl_label_frame": [vp, vp, u32, vp, u32, vp],
+        "lbl_label_frame_noalloc": [vp, vp, u32, vp, vp],
         "lbl_label_batch": [ctypes.POINTER(Job), ctypes.c_size_t, u32, vp],
         "lbl_tune": [vp, vp, u32, u32, vp],
         "lbl_tune_batch": [ctypes.POINTER(Job), ctypes.c_size_t, vp],
@@ -234,6 +235,12 @@ def abstraction_info(a: int) -> dict:
 
 def label_frame(a: int, O, n_props: int, L, flags: int = 0, stream=None) -> None:
     _check(lib().lbl_label_frame(a, _addr(O), n_props, _addr(L), flags, _stream(stream)))
+
+
+def label_frame_noalloc(a: int, O, n_props: int, L, stream=None) -> None:
+    """lbl_label_frame_noalloc: device O and L; intermediates in the library's
+    static device array (no allocation)."""
+    _check(lib().lbl_label_frame_noalloc(a, _addr(O), n_props, _addr(L), _stream(stream)))
 
 
 SHAPE_RECT, SHAPE_DISC = 0, 1
