@@ -51,9 +51,19 @@ struct GroupDesc {
     const uint16_t *sp_row;
     const uint64_t *sp_val;
     uint64_t max_entry;
-    uint64_t *P;                 // [G64][n_tiles][kRowBlock]
+    uint64_t *P;                 // [G64][n_tiles][kRowBlock] (null when fused)
     uint32_t n_tiles;
     uint32_t n_rb;
+    uint32_t fused;              // one tile per row block: tiles write the label bytes
+    uint32_t nx;                 // grid width in cells (row-major cell ids)
+    uint32_t morton;             // 1: the caller's cell ids are z-order
+    uint32_t pad;
+};
+
+// Sparse plans: one wavefront per (group, lane group, words [w0, w1)) packs
+// the nibble tables of those words for the lane group.
+struct PackItem {
+    uint32_t group, gi, w0, w1;
 };
 
 // Sparse plans: one workgroup per (group, tile, lane group).
@@ -121,7 +131,8 @@ struct BatchPlan {
     std::vector<TileItem> tiles;    // in queue order: XCD x's queue is tiles[xcd_start[x] .. xcd_start[x + 1])
     std::vector<uint32_t> xcd_start;  // kXcds + 1 entries (sparse plans)
     std::vector<uint32_t> launch;   // one-workgroup-per-tile launches: workgroup b runs tiles[launch[b]]
-    std::vector<CombineItem> combines;
+    std::vector<CombineItem> combines;  // empty for fused passes
+    std::vector<PackItem> packs;
     std::vector<const lbl_abs *> group_abs;  // abstraction of each group
     int default_tiling = 1;         // sparse: tiling index used when the tile does not choose one
     int tiling = 0;                 // sparse: index of the tilings every pass uses (set by plan_finalize)
@@ -157,16 +168,17 @@ struct BatchBuffers {
     uint32_t *d_xcd_start = nullptr;
     uint32_t *d_queues = nullptr;   // kXcds queue counters (zeroed by a kernel before each launch)
     CombineItem *d_combines = nullptr;
+    PackItem *d_packs = nullptr;
     SegDesc *d_segs = nullptr;
     uint32_t *d_lg_seg = nullptr;
     uint64_t *d_p = nullptr;
 };
 
 // Sparse batch kernels (defined with the sparse layout's kernels).
-// Pack: one wavefront per (group, word, lane group) -> the word's nibble
-// tables for the lane group's columns.
-hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const uint64_t *d_prefix, uint32_t n_groups,
-                                    uint64_t n_units, hipStream_t s);
+// Pack: one wavefront per pack item (group, lane group, word range) -> the
+// words' nibble tables for the lane group's columns.
+hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const PackItem *d_packs, uint32_t n_packs,
+                                    hipStream_t s);
 // Tiles: persistent (one workgroup per CU, per-XCD queues with stealing;
 // d_queues zeroed first) or one workgroup per tile in launch order.
 hipError_t launch_tiles_batch(const GroupDesc *d_groups, const TileItem *d_tiles, const uint32_t *d_launch,

@@ -151,6 +151,12 @@ k_seg_fill(const uint64_t *__restrict__ wm_ptr, const uint32_t *__restrict__ wm_
 
 // ---------------------------------------------------------------- per frame
 
+// Native vector types: loads and stores of these through address-space
+// qualified pointers compile (HIP's vector structs assign only in the
+// generic address space).
+typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+
 
 // One wavefront per word, one lane per cell: the mask of the propositions
 // cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  With
@@ -222,7 +228,7 @@ __device__ __forceinline__ uint32_t lds_addr(const uint64_t *p)
 // Copy of one word's nibble tables (as written by write_tables) into an LDS
 // table slot whose rows are kTabRow entries apart; lane l holds entries
 // 4l .. 4l + 3 (row l / 4).
-__device__ __forceinline__ void copy_tables(const ulonglong2 (&v)[2], uint64_t *t, uint32_t lane)
+__device__ __forceinline__ void copy_tables(const v2u64 (&v)[2], uint64_t *t, uint32_t lane)
 {
     uint64_t *e = t + (lane >> 2) * kTabRow + (lane & 3u) * 4;
     e[0] = v[0].x;
@@ -232,15 +238,15 @@ __device__ __forceinline__ void copy_tables(const ulonglong2 (&v)[2], uint64_t *
 }
 
 // One tile: its wavefronts walk their tasks, OR-ing labels into the row
-// block's accumulators, then the accumulators become the tile's partials
-// Pt[0 .. kRowBlock).  Tg + w * tg_stride holds the 256 nibble-table entries
-// of word w.
+// block's accumulators lds[0 .. kRowBlock), which hold the tile's labels when
+// it returns (after a workgroup barrier).  Tg + w * tg_stride holds the 256
+// nibble-table entries of word w.
 template <int WAVES>
-__device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, const SpRound *__restrict__ rounds,
-                                          const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
-                                          const uint64_t *__restrict__ Tg, uint64_t tg_stride,
-                                          uint64_t *__restrict__ Pt, uint64_t *lds,
-                                          const uint16_t *__restrict__ slot_row = nullptr, uint32_t n_slot = 0)
+__device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_tasks,
+                                                const SpRound *__restrict__ rounds,
+                                                const uint16_t *__restrict__ sp_row,
+                                                const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg,
+                                                uint64_t tg_stride, uint64_t *lds)
 {
     const uint32_t lane = threadIdx.x & 63;
     // uniform across the wavefront: task fields and round records become
@@ -248,17 +254,32 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t *acc = lds;                                  // kRowBlock accumulators
     uint64_t *tab = lds + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
-    const SpTask tk = wg_tasks[wave];
-    const uint32_t n = tk.n_rounds;
+    // Every array read here is device memory.  The batch path takes these
+    // pointers from its descriptors in memory, where the compiler cannot see
+    // their address space: without the casts it would issue flat loads,
+    // which count on the LDS wait counter too, so that every wait for the
+    // LDS would also wait for them.  The task's fields are moved to scalar
+    // registers for the same reason (loads through such pointers land in
+    // vector registers).
+    typedef __attribute__((address_space(1))) const uint32_t gu32;
+    typedef __attribute__((address_space(1))) const uint16_t gu16;
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
+    typedef __attribute__((address_space(1))) const v2u64 gu128;
+    const gu32 *task = (const gu32 *)(wg_tasks + wave);
+    const uint64_t tk_lo = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)task[0]) |
+                           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)task[1]) << 32);
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)task[2]);
+    const uint32_t round0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)task[3]);
+    static_assert(sizeof(SpTask) == 16, "task layout: lo, n_rounds, round0");
     {
-        const SpRound *rr = rounds + tk.round0;
+        const gu32 *rr = (const gu32 *)(rounds + round0);
 
         struct Stage {
             uint32_t rec;      // lanes 0-3: the record of the stage's next round
             uint32_t meta;
             uint64_t x;        // this lane's word value
             uint16_t r;        // its local row
-            ulonglong2 tb[2];  // this lane's 32 bytes of the table the round builds
+            v2u64 tb[2];       // this lane's 32 bytes of the table the round builds
         };
         // kStages rounds are in flight: round i is fetched (its entries and
         // table data loaded) kStages - 1 rounds before it is processed, and
@@ -272,11 +293,10 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
         // validity is applied when the round is processed.  Each load takes a
         // wavefront-uniform base and a per-lane offset, so that no per-lane
         // 64-bit address arithmetic is needed.
-        auto load_rec = [&](uint32_t i) {
-            return reinterpret_cast<const uint32_t *>(rr + min(i, n - 1))[lane & 3u];
-        };
-        const uint64_t *val_t = sp_val + tk.lo;
-        const uint16_t *row_t = sp_row + tk.lo;
+        auto load_rec = [&](uint32_t i) { return rr[(uint64_t)min(i, n - 1) * 4 + (lane & 3u)]; };
+        static_assert(sizeof(SpRound) == 16, "a round record is four dwords");
+        const gu64 *val_t = (const gu64 *)(sp_val + tk_lo);
+        const gu16 *row_t = (const gu16 *)(sp_row + tk_lo);
         auto fetch = [&](Stage &st, uint32_t i) {
             // the fields are read before the register is reloaded, so that the
             // reload can take the same register (no copy waiting for it)
@@ -290,7 +310,7 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
             // wavefront (still unconditionally): the 2 KiB of its last table
             // would mostly come from L2, the 16 wavefronts' last tables
             // filling the CU's L1
-            const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(Tg + (uint64_t)tword * tg_stride);
+            const gu128 *src = (const gu128 *)(Tg + (uint64_t)tword * tg_stride);
             const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? 2 * lane : 0u;
             st.tb[0] = src[tl];
             st.tb[1] = src[tl + 1];
@@ -380,18 +400,28 @@ __device__ __forceinline__ void tile_body(const SpTask *__restrict__ wg_tasks, c
         }
     }
     __syncthreads();
-    // streaming stores: the partials are read once, by the combine kernel
-    if (slot_row) {
-        // only the rows this tile touches, in its slots
-        for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES)
-            __builtin_nontemporal_store(acc[slot_row[k]], Pt + k);
-        return;
-    }
+}
+
+// The tile's accumulators as its partials: every row of the block at
+// Pt[0 .. kRowBlock), or (compact) only the n_slot rows slot_row[..] it
+// touches at Pt[0 .. n_slot).  Streaming stores: the partials are read once,
+// by the combine kernel.
+template <int WAVES>
+__device__ __forceinline__ void write_partials(const uint64_t *acc, uint64_t *__restrict__ Pt)
+{
     for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES) {
         const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(acc)[i];
         __builtin_nontemporal_store(v.x, Pt + 2 * i);
         __builtin_nontemporal_store(v.y, Pt + 2 * i + 1);
     }
+}
+
+template <int WAVES>
+__device__ __forceinline__ void write_partials_compact(const uint64_t *acc, uint64_t *__restrict__ Pt,
+                                                       const uint16_t *__restrict__ slot_row, uint32_t n_slot)
+{
+    for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES)
+        __builtin_nontemporal_store(acc[slot_row[k]], Pt + k);
 }
 
 // One workgroup per tile of a single frame: workgroup b runs tile
@@ -406,13 +436,12 @@ k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict_
 {
     extern __shared__ uint64_t lds[];
     const uint32_t tile = block_tile[blockIdx.x];
+    tile_accumulate<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256, lds);
     if (tile_slot) {
         const uint32_t s0 = tile_slot[tile], s1 = tile_slot[tile + 1];
-        tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256, P + s0, lds,
-                         slot_row + s0, s1 - s0);
+        write_partials_compact<WAVES>(lds, P + s0, slot_row + s0, s1 - s0);
     } else {
-        tile_body<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256,
-                         P + (uint64_t)tile * kRowBlock, lds);
+        write_partials<WAVES>(lds, P + (uint64_t)tile * kRowBlock);
     }
 }
 
@@ -434,16 +463,119 @@ __device__ __forceinline__ uint64_t row_slots_or(const uint64_t *__restrict__ P,
     return bits;
 }
 
+// The label bytes of rows [t0, t0 + n) of one job (n <= 64), written as one
+// contiguous block L[t0 * np .. (t0 + n) * np): lane r holds the job's bits
+// of row t0 + r in v (bit p = proposition p).  The block is staged in LDS at
+// its offset modulo 16 (each lane ORs its row's bytes into 4-byte-aligned
+// words; neighbouring rows share the words at their boundary), then written
+// with 16-byte stores; the units at the block's two ends, which also hold
+// bytes of other rows, are written byte by byte, so no byte outside the
+// block is stored.  stage: 64 * 64 + 32 bytes of this wavefront's LDS (the
+// last row's words reach at most 2 bytes past the block).
+__device__ __forceinline__ void emit_block(uint32_t *stage, uint32_t lane, uint32_t n, uint64_t v, uint8_t *dst,
+                                           uint32_t np)
+{
+    const uintptr_t base = reinterpret_cast<uintptr_t>(dst);
+    const uint32_t mis = (uint32_t)(base & 15u);
+    const uint32_t total = mis + n * np;  // staged bytes, <= 15 + 4096
+    const uint32_t n_units = (total + 15) >> 4;
+    v4u32 *st4 = reinterpret_cast<v4u32 *>(stage);
+    for (uint32_t u = lane; u < n_units; u += 64) st4[u] = v4u32{0u, 0u, 0u, 0u};
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const uint32_t o = mis + lane * np;
+        const uint32_t sh = 8 * (o & 3u);
+        uint32_t *w = stage + (o >> 2);
+        const uint32_t nq = ((o & 3u) + np + 3) >> 2;
+        uint32_t prev = 0;
+        for (uint32_t q = 0; q < nq; ++q) {
+            const uint32_t cur = 4 * q < np ? spread_nib((uint32_t)(v >> (4 * q)) & 0xFu) : 0u;
+            const uint32_t out = sh ? (cur << sh) | (prev >> (32 - sh)) : cur;
+            __hip_atomic_fetch_or(w + q, out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            prev = cur;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // device memory (flat stores would also count on the LDS wait counter)
+    __attribute__((address_space(1))) uint8_t *g = (__attribute__((address_space(1))) uint8_t *)(dst - mis);
+    for (uint32_t u = lane; u < n_units; u += 64) {
+        const v4u32 x = st4[u];
+        const uint32_t lo = 16 * u, hi = lo + 16;
+        if (lo >= mis && hi <= total) {
+            *(__attribute__((address_space(1))) v4u32 *)(g + lo) = x;
+        } else {
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            for (uint32_t b = 0; b < 16; ++b)
+                if (lo + b >= mis && lo + b < total) g[lo + b] = (uint8_t)(xs[b >> 2] >> (8 * (b & 3u)));
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the stage is reused by the next block
+}
+
+// A job's descriptor with every field in scalar registers (read through a
+// pointer held in the batch's descriptors, the fields would otherwise land in
+// vector registers and make the loops over them lane-divergent).
+__device__ __forceinline__ SegDesc uniform_seg(const SegDesc *segs, uint32_t i)
+{
+    const SegDesc d = segs[i];
+    auto u32 = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
+    auto ptr = [&](uintptr_t p) { return ((uintptr_t)u32((uint32_t)(p >> 32)) << 32) | u32((uint32_t)p); };
+    SegDesc r;
+    r.O = reinterpret_cast<const uint8_t *>(ptr(reinterpret_cast<uintptr_t>(d.O)));
+    r.L = reinterpret_cast<uint8_t *>(ptr(reinterpret_cast<uintptr_t>(d.L)));
+    r.n_props = u32(d.n_props);
+    r.bit = u32(d.bit);
+    return r;
+}
+
+// LDS of one wavefront's label-byte staging (emit_block): 64 rows of at
+// most 64 bytes at an offset below 16, plus the word a row's last bytes may
+// spill into.
+constexpr uint32_t kStageWords = (64 * 64 + 32) / 4;
+static_assert(kTileWaves * kStageWords * 4 <= kTileWaves * kRing * kTabWords * 8,
+              "label staging must fit in the tile's table slots");
+
+// Label bytes of a whole row block straight from a tile's accumulators (the
+// batch tilings with one tile per row block: the accumulators hold the final
+// labels of the block's rows for the lane group's 64 columns).  Wavefront w
+// takes the 64-row chunks w, w + WAVES, ... of the block, and for every job
+// of the lane group writes the chunk's label bytes as one contiguous block
+// (emit_block), staged in the LDS the wavefronts' table slots used.
+template <int WAVES>
+__device__ __forceinline__ void emit_tile(uint64_t *lds, const GroupDesc &g, uint32_t gi, uint32_t rb)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds + kRowBlock) + wave * kStageWords;
+    const uint64_t t_base = (uint64_t)rb * kRowBlock;
+    const uint32_t n_rows = (uint32_t)min<uint64_t>(kRowBlock, g.n_traj - t_base);
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[gi]);
+    const uint32_t s1 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[gi + 1]);
+    for (uint32_t c0 = wave * 64; c0 < n_rows; c0 += 64 * WAVES) {
+        const uint32_t n = min(64u, n_rows - c0);
+        const uint64_t bits = lane < n ? lds[c0 + lane] : 0ull;
+        for (uint32_t sgi = s0; sgi < s1; ++sgi) {
+            const SegDesc d = uniform_seg(g.segs, sgi);
+            const uint64_t v = d.n_props >= 64 ? bits : (bits >> d.bit) & ((1ull << d.n_props) - 1ull);
+            emit_block(stage, lane, n, v, d.L + (t_base + c0) * d.n_props, d.n_props);
+        }
+    }
+}
+
 // One tile item of a batch: pass it.group, tile it.tile, lane group it.gi.
-// The pass's nibble tables are [w][G64][256], its partials
-// [G64][n_tiles][kRowBlock].
+// The pass's nibble tables are [w][G64][256].  Passes on a tiling with one
+// tile per row block (fused) write the label bytes themselves; the others
+// write partials [G64][n_tiles][kRowBlock] for k_combine_batch.
 template <int WAVES>
 __device__ __forceinline__ void batch_tile(const GroupDesc *__restrict__ groups, const TileItem &it, uint64_t *lds)
 {
     const GroupDesc &g = groups[it.group];
-    tile_body<WAVES>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
-                     g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256,
-                     g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock, lds);
+    tile_accumulate<WAVES>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
+                           g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256, lds);
+    if (g.fused)
+        emit_tile<WAVES>(lds, g, it.gi, it.tile);
+    else
+        write_partials<WAVES>(lds, g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock);
 }
 
 // One workgroup per tile item: workgroup b runs items[launch[b]].
@@ -492,54 +624,120 @@ k_label_tiles_queue(const GroupDesc *__restrict__ groups, const TileItem *__rest
     }
 }
 
-// Bit p set iff byte p of src[0 .. n) is non-zero, 1 <= n <= 64, any
-// alignment: the 4-byte-aligned words holding those bytes are loaded (each
-// holds at least one byte of the range, so no load leaves the caller's
-// buffer's pages) and bytes outside the range are dropped.
-__device__ __forceinline__ uint64_t byte_mask_any(const uint8_t *src, uint32_t n)
+// Bit p set iff byte mis + p of the dwords p[0 ..] is non-zero, for p < n
+// (1 <= n <= 64, mis < 4).  Reads p[0 .. (n + 6) / 4] whatever mis is (the
+// caller's array extends that far); dwords past the range are dropped.
+__device__ __forceinline__ uint64_t byte_mask_words(const uint32_t *p, uint32_t mis, uint32_t n)
 {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(src);
-    const uint32_t mis = (uint32_t)(a & 3u);
-    const uint32_t *p = reinterpret_cast<const uint32_t *>(a - mis);
     const uint32_t nd = (mis + n + 3) >> 2;  // this lane's words: 1 .. 17
     const uint32_t kmax = (n + 6) >> 2;      // an upper bound of nd for every lane
     uint64_t lo = 0;
 #pragma unroll
     for (uint32_t k = 0; k < 16; ++k)
-        if (k < kmax) {
-            const uint32_t v = k < nd ? p[k] : 0u;
-            lo |= (uint64_t)nz_bytes(v) << (4 * k);
+        if (k < kmax) {  // uniform
+            // dwords past this lane's range are dropped by a mask, not a branch
+            const uint32_t keep = 0u - (uint32_t)(k < nd);
+            lo |= (uint64_t)(nz_bytes(p[k]) & keep) << (4 * k);
         }
-    const uint32_t hi = (kmax > 16 && nd > 16) ? nz_bytes(p[16]) : 0u;
+    const uint32_t hi = kmax > 16 ? nz_bytes(p[16]) & (0u - (uint32_t)(nd > 16)) : 0u;
     const uint64_t m = mis ? (lo >> mis) | ((uint64_t)hi << (64 - mis)) : lo;
     return n >= 64 ? m : m & ((1ull << n) - 1ull);
 }
 
-// One wavefront per (pass, word, lane group): lane b holds cell b of the
-// word; for every job of the lane group it reads the cell's n_props bytes of
-// that job's O (contiguous) into the job's columns of the cell's mask, then
-// the word's nibble tables for the lane group are written.
+// LDS words a pack wavefront stages one job's bytes of one word in: 8 runs
+// of 8 cells (or one of 64) of at most 64 bytes, each from a dword boundary,
+// plus the dwords byte_mask_words may read past the last run.
+constexpr uint32_t kPackStaged = 8 * ((3 + 8 * 64 + 3) / 4);
+static_assert(kPackStaged >= (3 + 64 * 64 + 3) / 4, "a 64-cell run must fit the stage");
+constexpr uint32_t kPackStageWords = kPackStaged + 4;
+// Dword loads per lane in flight while a stage is filled.
+constexpr uint32_t kPackLoads = 9;
+
+typedef __attribute__((address_space(1))) const uint32_t global_u32;
+typedef __attribute__((address_space(1))) const uint64_t global_u64;
+
+// One wavefront per pack item (pass, lane group, words [w0, w1)): for each
+// word, lane b builds the proposition mask of the word's cell b over the
+// lane group's columns, then the word's nibble tables for the lane group are
+// written.  A job's bytes of the word's 64 cells are n_props-byte records in
+// 8 runs of 8 consecutive cells (row-major ids: one run per cell row of the
+// 8 x 8 tile, nx cells apart) or one run of 64 (z-order ids); they are
+// staged in LDS with coalesced dword loads (every run starts at the same
+// offset within a dword, since cell ids of a run start are multiples of 8),
+// and each lane then reads its cell's record from LDS.
 __global__ void __launch_bounds__(256)
-k_pack_batch_tables(const GroupDesc *__restrict__ groups, const uint64_t *__restrict__ prefix, uint32_t n_groups,
-                    uint64_t n_units)
+k_pack_batch_tables(const GroupDesc *__restrict__ groups, const PackItem *__restrict__ items, uint32_t n_items)
 {
+    __shared__ uint32_t stage_all[4][kPackStageWords];
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t u = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-         u < n_units; u += waves) {
-        uint32_t gidx = 0;
-        while (gidx + 1 < n_groups && prefix[gidx + 1] <= u) ++gidx;
-        const GroupDesc &g = groups[gidx];
-        const uint64_t local = u - prefix[gidx];
-        const uint32_t G = g.G64;
-        const uint32_t w = (uint32_t)(local / G), gi = (uint32_t)(local % G);
-        const uint64_t cell = g.word_cell[(uint64_t)w * 64 + lane];
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t i = blockIdx.x * 4 + wv;
+    if (i >= n_items) return;  // whole wavefronts
+    uint32_t *stage = stage_all[wv];
+    const PackItem it = items[i];
+    const GroupDesc &g = groups[it.group];
+    // values read through pointers held in the descriptors come back in
+    // vector registers; they are wavefront-uniform, and are moved to scalar
+    // registers so that the loops and offsets derived from them are scalar
+    auto uni = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
+    const uint32_t s0 = uni(g.lg_seg[it.gi]), s1 = uni(g.lg_seg[it.gi + 1]);
+    const bool zo = g.morton != 0;
+    // lane b is the cell at (dx, dy) of the word's 8 x 8 tile, x taking the
+    // odd bits of b; in z-order ids it is the word's cell b
+    const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
+    const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
+    const uint32_t n_run = zo ? 1u : 8u, run_cells = zo ? 64u : 8u;
+    const uint32_t my_run = zo ? 0u : dy, my_pos = zo ? lane : dx;
+    const global_u32 *word_cell = (const global_u32 *)g.word_cell;
+    for (uint32_t w = it.w0; w < it.w1; ++w) {
+        // the word's first cell (dx = dy = 0), wavefront-uniform (read into
+        // a scalar register, so that everything derived from it is scalar)
+        const uint32_t c0 = zo ? w * 64 : word_cell[(uint64_t)w * 64];
+        const uint64_t cell0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c0);
         uint64_t m = 0;
-        for (uint32_t sgi = g.lg_seg[gi], s1 = g.lg_seg[gi + 1]; sgi < s1; ++sgi) {
+        for (uint32_t sgi = s0; sgi < s1; ++sgi) {
             const SegDesc d = g.segs[sgi];
-            m |= byte_mask_any(d.O + cell * d.n_props, d.n_props) << d.bit;
+            const uint32_t np = uni(d.n_props), bit = uni(d.bit);
+            const uintptr_t o_addr = ((uintptr_t)uni((uint32_t)((uintptr_t)d.O >> 32)) << 32) | uni((uint32_t)(uintptr_t)d.O);
+            const uintptr_t a0 = o_addr + cell0 * np;
+            const uint32_t mis = (uint32_t)(a0 & 3u);
+            const uint32_t nd = (mis + run_cells * np + 3) >> 2;  // dwords per run, >= 2
+            // byte offsets from base fit 32 bits: 7 runs of nx * np bytes
+            // (nx * ny < 2^31 cells, np <= 64) plus one run's dwords
+            const uint32_t run_stride = zo ? 0u : g.nx * np;
+            const __attribute__((address_space(1))) uint8_t *base =
+                reinterpret_cast<const __attribute__((address_space(1))) uint8_t *>(a0 - mis);
+            // floor(q / nd) as umulhi(q, magic): exact for q * nd < 2^32
+            const uint32_t magic = 0xFFFFFFFFu / nd + 1u;
+            const uint32_t total = n_run * nd;  // <= kPackStageWords
+            // the loads of a phase (up to kPackLoads per lane) are all issued
+            // before the first is stored, so the wavefront waits for memory
+            // once per phase: once per job and word up to 35 propositions
+            // (8 runs of at most 72 dwords), twice above
+            // Lanes past the end take the last dword again (loaded and
+            // stored twice with the same value), so no lane branches.
+            for (uint32_t q0 = 0; q0 < total; q0 += 64 * kPackLoads) {
+                uint32_t v[kPackLoads], at[kPackLoads];
+#pragma unroll
+                for (uint32_t k = 0; k < kPackLoads; ++k)
+                    if (q0 + 64 * k < total) {  // uniform
+                        const uint32_t q = min(q0 + lane + 64 * k, total - 1);
+                        const uint32_t r = __umulhi(q, magic), j = q - r * nd;
+                        at[k] = q;
+                        v[k] = *reinterpret_cast<const global_u32 *>(base + (r * run_stride + 4u * j));
+                    }
+#pragma unroll
+                for (uint32_t k = 0; k < kPackLoads; ++k)
+                    if (q0 + 64 * k < total) stage[at[k]] = v[k];
+            }
+            // LDS instructions of a wavefront complete in issue order; the
+            // barrier keeps the compiler from moving the reads above the writes
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t off = my_run * nd * 4 + mis + my_pos * np;
+            m |= byte_mask_words(stage + (off >> 2), off & 3u, np) << bit;
+            __builtin_amdgcn_wave_barrier();  // the next job overwrites the stage
         }
-        write_tables(m, g.Ow + ((uint64_t)w * G + gi) * 256, lane);
+        write_tables(m, g.Ow + ((uint64_t)w * g.G64 + it.gi) * 256, lane);
     }
 }
 
@@ -547,67 +745,23 @@ k_pack_batch_tables(const GroupDesc *__restrict__ groups, const uint64_t *__rest
 __device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile,
                                                  uint64_t t)
 {
+    // device memory (the batch passes pointers read from its descriptors:
+    // without the casts they would be flat loads)
+    const __attribute__((address_space(1))) uint64_t *Pg = (const __attribute__((address_space(1))) uint64_t *)P;
+    const __attribute__((address_space(1))) uint32_t *rbt = (const __attribute__((address_space(1))) uint32_t *)rb_tile;
     const uint64_t rb = t / kRowBlock, loc = t % kRowBlock;
-    const uint32_t k0 = rb_tile[rb], k1 = rb_tile[rb + 1];
+    const uint32_t k0 = rbt[rb], k1 = rbt[rb + 1];
     uint64_t bits = 0;
     // sixteen loads in flight at a time: indices past the block's last tile
     // read that tile again, which leaves the OR unchanged
     for (uint32_t kb = k0; kb < k1; kb += 16) {
         uint64_t v[16];
 #pragma unroll
-        for (uint32_t j = 0; j < 16; ++j) v[j] = P[(uint64_t)min(kb + j, k1 - 1) * kRowBlock + loc];
+        for (uint32_t j = 0; j < 16; ++j) v[j] = Pg[(uint64_t)min(kb + j, k1 - 1) * kRowBlock + loc];
 #pragma unroll
         for (uint32_t j = 0; j < 16; ++j) bits |= v[j];
     }
     return bits;
-}
-
-// The label bytes of rows [t0, t0 + n) of one job (n <= 64), written as one
-// contiguous block L[t0 * np .. (t0 + n) * np): lane r holds the job's bits
-// of row t0 + r in v (bit p = proposition p).  The block is staged in LDS at
-// its offset modulo 16 (each lane ORs its row's bytes into 4-byte-aligned
-// words; neighbouring rows share the words at their boundary), then written
-// with 16-byte stores; the units at the block's two ends, which also hold
-// bytes of other rows, are written byte by byte, so no byte outside the
-// block is stored.  stage: 64 * 64 + 32 bytes of this wavefront's LDS (the
-// last row's words reach at most 2 bytes past the block).
-__device__ __forceinline__ void emit_block(uint32_t *stage, uint32_t lane, uint32_t n, uint64_t v, uint8_t *dst,
-                                           uint32_t np)
-{
-    const uintptr_t base = reinterpret_cast<uintptr_t>(dst);
-    const uint32_t mis = (uint32_t)(base & 15u);
-    const uint32_t total = mis + n * np;  // staged bytes, <= 15 + 4096
-    const uint32_t n_units = (total + 15) >> 4;
-    uint4 *st4 = reinterpret_cast<uint4 *>(stage);
-    for (uint32_t u = lane; u < n_units; u += 64) st4[u] = make_uint4(0u, 0u, 0u, 0u);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < n) {
-        const uint32_t o = mis + lane * np;
-        const uint32_t sh = 8 * (o & 3u);
-        uint32_t *w = stage + (o >> 2);
-        const uint32_t nq = ((o & 3u) + np + 3) >> 2;
-        uint32_t prev = 0;
-        for (uint32_t q = 0; q < nq; ++q) {
-            const uint32_t cur = 4 * q < np ? spread_nib((uint32_t)(v >> (4 * q)) & 0xFu) : 0u;
-            const uint32_t out = sh ? (cur << sh) | (prev >> (32 - sh)) : cur;
-            __hip_atomic_fetch_or(w + q, out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            prev = cur;
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    uint8_t *g = dst - mis;
-    for (uint32_t u = lane; u < n_units; u += 64) {
-        const uint4 x = st4[u];
-        const uint32_t lo = 16 * u, hi = lo + 16;
-        if (lo >= mis && hi <= total) {
-            *reinterpret_cast<uint4 *>(g + lo) = x;
-        } else {
-            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-            for (uint32_t b = 0; b < 16; ++b)
-                if (lo + b >= mis && lo + b < total) g[lo + b] = (uint8_t)(xs[b >> 2] >> (8 * (b & 3u)));
-        }
-    }
-    __builtin_amdgcn_wave_barrier();  // the stage is reused by the next block
 }
 
 // One wavefront per (pass, lane group, rows [row0, row1)), 64 rows at a
@@ -625,13 +779,14 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
     const CombineItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
     const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_tiles * kRowBlock;
-    const uint32_t s0 = g.lg_seg[it.gi], s1 = g.lg_seg[it.gi + 1];
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[it.gi]);
+    const uint32_t s1 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[it.gi + 1]);
     for (uint64_t t0 = it.row0; t0 < it.row1; t0 += 64) {
         const uint64_t t = t0 + lane;
         const uint64_t bits = t < it.row1 ? row_partials(Pg, g.sp_rb_tile, t) : 0ull;
         const uint32_t n = (uint32_t)min<uint64_t>(64, it.row1 - t0);
         for (uint32_t sgi = s0; sgi < s1; ++sgi) {
-            const SegDesc d = g.segs[sgi];
+            const SegDesc d = uniform_seg(g.segs, sgi);
             const uint64_t v = d.n_props >= 64 ? bits : (bits >> d.bit) & ((1ull << d.n_props) - 1ull);
             emit_block(stage, lane, n, v, d.L + t0 * d.n_props, d.n_props);
         }
@@ -980,13 +1135,11 @@ SparseLayout::~SparseLayout()
 
 void free_sparse(SparseLayout *sp) { delete sp; }
 
-hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const uint64_t *d_prefix, uint32_t n_groups,
-                                    uint64_t n_units, hipStream_t s)
+hipError_t launch_pack_batch_tables(const GroupDesc *d_groups, const PackItem *d_packs, uint32_t n_packs,
+                                    hipStream_t s)
 {
-    if (n_units == 0) return hipSuccess;
-    const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((n_units + 3) / 4, 1u << 16));
-    hipLaunchKernelGGL(k_pack_batch_tables, dim3((unsigned)blocks), dim3(256), 0, s, d_groups, d_prefix, n_groups,
-                       n_units);
+    if (n_packs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_batch_tables, dim3((n_packs + 3) / 4), dim3(256), 0, s, d_groups, d_packs, n_packs);
     return hipGetLastError();
 }
 

@@ -131,10 +131,35 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
         const SpTiling &tl = p.group_abs[g]->sp->tilings[p.tiling];
         CHECK(d.n_tiles == tl.n_tiles && d.sp_tasks == tl.tasks && d.sp_rounds == tl.rounds && d.sp_rb_tile == tl.rb_tile);
         CHECK(d.n_rb == (uint32_t)((d.n_traj + kRowBlock - 1) / kRowBlock));
+        // fused passes (one tile per row block) write labels from the tiles
+        // and have no partials
+        CHECK(d.fused == (d.n_tiles == d.n_rb ? 1u : 0u));
+        want_tiles += (uint64_t)d.n_tiles * d.G64;
+        if (d.fused) {
+            CHECK(d.P == nullptr);
+            for (uint32_t rb = 0; rb < d.n_rb; ++rb) CHECK(tl.rb_tile_host[rb] == rb);
+            continue;
+        }
         const size_t pb = (size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t);
         CHECK(inside(d.P, pb));
         p_ranges.push_back({reinterpret_cast<const uint8_t *>(d.P), reinterpret_cast<const uint8_t *>(d.P) + pb});
-        want_tiles += (uint64_t)d.n_tiles * d.G64;
+    }
+    // pack items: every (pass, lane group, word) exactly once
+    CHECK(inside(b.d_packs, p.packs.size() * sizeof(PackItem)));
+    {
+        std::map<std::pair<uint32_t, uint32_t>, std::vector<uint8_t>> words;
+        for (const PackItem &k : p.packs) {
+            CHECK(k.group < p.groups.size() && k.gi < p.groups[k.group].G64);
+            CHECK(k.w0 < k.w1 && k.w1 <= p.groups[k.group].n_words);
+            auto &v = words[std::make_pair(k.group, k.gi)];
+            v.resize(p.groups[k.group].n_words, 0);
+            for (uint32_t w = k.w0; w < k.w1 && w < v.size(); ++w) ++v[w];
+        }
+        uint64_t want_pairs = 0;
+        for (const GroupDesc &d : p.groups) want_pairs += d.G64;
+        CHECK(words.size() == want_pairs);
+        for (auto &kv : words)
+            for (uint8_t c : kv.second) CHECK(c == 1);
     }
     for (size_t i = 0; i < p_ranges.size(); ++i) {
         CHECK(p_ranges[i].second <= ow_ranges.front().first || p_ranges[i].first >= ow_ranges.back().second);
@@ -180,9 +205,16 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> rows;
     for (const CombineItem &c : p.combines) {
         CHECK(c.group < p.groups.size() && c.gi < p.groups[c.group].G64);
+        CHECK(!p.groups[c.group].fused);
         CHECK(c.row0 < c.row1 && c.row1 <= p.groups[c.group].n_traj && c.row0 % 64 == 0);
         rows[std::make_pair(c.group, c.gi)] += c.row1 - c.row0;
     }
+    // a fused pass's tile (row block rb, lane group gi) writes the rows of rb
+    for (const TileItem &t : p.tiles)
+        if (p.groups[t.group].fused) {
+            const uint64_t r0 = (uint64_t)t.tile * kRowBlock;
+            rows[std::make_pair(t.group, t.gi)] += std::min<uint64_t>(kRowBlock, p.groups[t.group].n_traj - r0);
+        }
     for (size_t g = 0; g < p.groups.size(); ++g)
         for (uint32_t gi = 0; gi < p.groups[g].G64; ++gi) {
             const uint64_t covered_rows = rows[std::make_pair((uint32_t)g, gi)];
@@ -195,16 +227,24 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
     std::map<const uint8_t *, std::vector<std::pair<uint64_t, uint64_t>>> blocks;
     std::map<const uint8_t *, uint64_t> job_bytes;
     for (const JobRef &j : jobs) job_bytes[j.L] = j.a->n_traj * j.n_props;
-    for (const CombineItem &c : p.combines) {
-        const uint32_t *lgs = p.lg_seg.data() + p.lgs_off[c.group];
-        for (uint64_t t0 = c.row0; t0 < c.row1; t0 += 64) {
-            const uint64_t n = std::min<uint64_t>(64, c.row1 - t0);
-            for (uint32_t sgi = lgs[c.gi]; sgi < lgs[c.gi + 1]; ++sgi) {
+    auto add_rows = [&](uint32_t g, uint32_t gi, uint64_t row0, uint64_t row1) {
+        const uint32_t *lgs = p.lg_seg.data() + p.lgs_off[g];
+        for (uint64_t t0 = row0; t0 < row1; t0 += 64) {
+            const uint64_t n = std::min<uint64_t>(64, row1 - t0);
+            for (uint32_t sgi = lgs[gi]; sgi < lgs[gi + 1]; ++sgi) {
                 const SegDesc &d = p.segs[sgi];
                 blocks[d.L].push_back({t0 * d.n_props, (t0 + n) * d.n_props});
             }
         }
-    }
+    };
+    for (const CombineItem &c : p.combines) add_rows(c.group, c.gi, c.row0, c.row1);
+    // fused tiles emit their block's rows in 64-row chunks (chunk starts are
+    // multiples of 64 from the block start, a multiple of kRowBlock)
+    for (const TileItem &t : p.tiles)
+        if (p.groups[t.group].fused) {
+            const uint64_t r0 = (uint64_t)t.tile * kRowBlock;
+            add_rows(t.group, t.gi, r0, std::min<uint64_t>(r0 + kRowBlock, p.groups[t.group].n_traj));
+        }
     CHECK(blocks.size() == job_bytes.size());
     // the store units of every block as the combine issues them: 16-byte
     // units only where they lie inside the block, single bytes where a unit
