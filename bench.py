@@ -125,6 +125,8 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
     sparse  : sparse layout (10 B per (row, word) entry + the one-frame
               tiling's task and round tables) + cell masks (W x 64 x 8 B)
               + label bits (8 B per row)                              -> HBM
+              (frames of at most 32 propositions: their own tiling's
+              tables, 4 B cell masks and 4 B of label bits per row)
     mfma    : 2 N_t N_c N_p int8 multiply-adds                         -> MFMA
     mfma_i8 : int8 T (1 B per cell of every row) + masks + L           -> HBM
     """
@@ -135,7 +137,9 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
         return {"bound": "mfma", "achieved": ops / t / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": ops / t / 1e12 / INT8_PEAK_TOPS, "traffic": None, "kernel": "label_mfma",
                 "kernel_ms": kernel_ms, "algorithmic_ops": ops}
-    if kernel == "sparse":
+    if kernel == "sparse" and n_props <= 32 and info.get("sparse_frame_bytes_narrow"):
+        alg, src, summary = info["sparse_frame_bytes_narrow"] + W * 64 * 4 + n_traj * 4, "sparse.hip", None
+    elif kernel == "sparse":
         alg, src, summary = info["sparse_frame_bytes"] + W * 64 * 8 + n_traj * 8, "sparse.hip", "label_sparse_200k_512_64_traffic.json"
     elif kernel == "mfma_i8":
         alg, src, summary = n_traj * W * 64 + W * 64 * 8 + n_traj * n_props, "label_mfma.hip", None

@@ -167,6 +167,11 @@ typedef struct {
                                     the rows of its compact partial slots */
     uint32_t sparse_tiles;   /* workgroups of a one-frame launch */
     uint32_t sparse_row_block; /* rows per row block of the sparse layout */
+    uint64_t sparse_frame_bytes_narrow; /* sparse_frame_bytes for frames of at
+                                           most 32 propositions (their own
+                                           tiling, 32-bit label masks) */
+    uint32_t sparse_tiles_narrow;       /* workgroups of such a launch */
+    uint32_t reserved;                  /* 0 */
 } lbl_abs_info;
 
 lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);

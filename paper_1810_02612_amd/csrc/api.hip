@@ -418,6 +418,9 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
     out->sparse_frame_bytes = 0;
     out->sparse_tiles = 0;
     out->sparse_row_block = 0;
+    out->sparse_frame_bytes_narrow = 0;
+    out->sparse_tiles_narrow = 0;
+    out->reserved = 0;
     if (a->sp) {
         const SparseLayout &sp = *a->sp;
         const SpTiling &t = sp.tilings[0];
@@ -430,6 +433,12 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
                                   t.n_rounds * sizeof(SpRound) + t.n_slots * sizeof(uint16_t);
         out->sparse_tiles = t.n_tiles;
         out->sparse_row_block = kRowBlock;
+        if ((int)sp.tilings.size() > kNarrowTiling) {
+            const SpTiling &u = sp.tilings[kNarrowTiling];
+            out->sparse_frame_bytes_narrow = entry_bytes + (uint64_t)u.n_tiles * kTileWaves * sizeof(SpTask) +
+                                             u.n_rounds * sizeof(SpRound) + u.n_slots * sizeof(uint16_t);
+            out->sparse_tiles_narrow = u.n_tiles;
+        }
     }
     return LBL_OK;
 }

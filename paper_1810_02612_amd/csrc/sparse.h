@@ -31,6 +31,9 @@ constexpr uint32_t kTabRow = 17;
 constexpr uint32_t kTabWords = 16 * kTabRow;
 // LDS of a tile workgroup: accumulators + every wavefront's tables.
 constexpr size_t kTileLds = ((size_t)kRowBlock + (size_t)kTileWaves * kRing * kTabWords) * sizeof(uint64_t);
+// The same with 32-bit masks (frames of at most 32 propositions): 66 KiB, so
+// two tile workgroups share a CU.
+constexpr size_t kTileLds32 = ((size_t)kRowBlock + (size_t)kTileWaves * kRing * kTabWords) * sizeof(uint32_t);
 
 // One wavefront's share of a tile: consecutive entries lo .. of one row
 // block, processed as rounds [round0, round0 + n_rounds).
@@ -89,13 +92,15 @@ struct SparseLayout {
     uint32_t n_used = 0;         // words held by some entry (their tables are packed per frame)
     uint32_t *used_words = nullptr;  // device [n_used] ascending, or null when every word is used
     // tilings[0]: one frame (about one tile per CU, tiles of equal cost);
-    // tilings[1 + i]: 2^i tiles per row block (batches)
+    // tilings[1 + i]: 2^i tiles per row block (batches); tilings[kNarrowTiling]:
+    // one frame of at most 32 propositions (about two tiles per CU)
     std::vector<SpTiling> tilings;
     size_t round_bytes = 0;      // device bytes of all tilings' tables
     ~SparseLayout();
 };
 
 constexpr int kBatchTilings = 4;  // 1, 2, 4, 8 tiles per row block
+constexpr int kNarrowTiling = 1 + kBatchTilings;
 
 // Build the tiled layout of a from its bitpacked T (sets a->sp).
 lbl_status build_sparse(lbl_abs *a);
@@ -125,7 +130,8 @@ lbl_status sparse_part(const uint64_t *T, uint32_t row_stride, uint64_t n_rows, 
 lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts);
 
 // Workspace bytes for one frame of n_lane_groups 64-column groups on tiling
-// t (cell masks + per-tile partial labels).
+// t (nibble tables + per-tile partial labels); for one frame (the defaults),
+// the larger of the 64-bit and the 32-bit mask paths.
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t = 0);
 
 // Pack O, label through the tiled layout, write L (device pointers).

@@ -165,9 +165,10 @@ typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 // taking the odd bits of b; with z-order ids (morton) lane b's cell is
 // w * 64 + b.  Wavefront i packs word words[i], or word i when words is null:
 // only words that some entry of the layout holds need tables.
+template <typename M>
 __global__ void __launch_bounds__(256)
 k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
-              uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tg)
+              uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, M *__restrict__ Tg)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -177,7 +178,11 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
     const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
     const uint64_t cell = morton ? (uint64_t)w * 64 + lane
                                  : (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
-    write_tables(byte_mask(O + cell * n_props, n_props), Tg + (uint64_t)w * 256, lane);
+    const uint64_t mask = byte_mask(O + cell * n_props, n_props);
+    if constexpr (sizeof(M) == 8)
+        write_tables(mask, Tg + (uint64_t)w * 256, lane);
+    else
+        write_tables32((uint32_t)mask, Tg + (uint64_t)w * 256, lane);
 }
 
 
@@ -211,49 +216,65 @@ __device__ __forceinline__ uint32_t select_by_lane(uint64_t mask, uint32_t a, ui
     return r;
 }
 
-typedef __attribute__((address_space(3))) const uint64_t lds_u64;
-
-// Entry of table row q at LDS byte address addr + q * kTabRow * 8.
-__device__ __forceinline__ uint64_t lds_entry(uint32_t addr, int q)
+// Entry (of mask type M) of table row q at LDS byte address
+// addr + q * kTabRow * sizeof(M).
+template <typename M>
+__device__ __forceinline__ M lds_entry(uint32_t addr, int q)
 {
-    return *reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(addr + q * kTabRow * 8));
+    return *reinterpret_cast<__attribute__((address_space(3))) const M *>(
+        static_cast<uintptr_t>(addr + q * kTabRow * sizeof(M)));
 }
 
 // LDS byte address of p.
-__device__ __forceinline__ uint32_t lds_addr(const uint64_t *p)
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
 {
-    return (uint32_t)reinterpret_cast<uintptr_t>((lds_u64 *)p);
+    return (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) const uint8_t *)p);
 }
+
+// Dwords of one word's nibble tables a lane holds while copying them:
+// 4 entries of M, 32 bytes (64-bit masks) or 16 (32-bit).
+template <typename M>
+constexpr uint32_t kTbDwords = sizeof(M);  // 4 entries x sizeof(M) / 4 bytes
 
 // Copy of one word's nibble tables (as written by write_tables) into an LDS
 // table slot whose rows are kTabRow entries apart; lane l holds entries
-// 4l .. 4l + 3 (row l / 4).
-__device__ __forceinline__ void copy_tables(const v2u64 (&v)[2], uint64_t *t, uint32_t lane)
+// 4l .. 4l + 3 (row l / 4) in tb.
+template <typename M>
+__device__ __forceinline__ void copy_tables(const v4u32 (&tb)[kTbDwords<M> / 4], M *t, uint32_t lane)
 {
-    uint64_t *e = t + (lane >> 2) * kTabRow + (lane & 3u) * 4;
-    e[0] = v[0].x;
-    e[1] = v[0].y;
-    e[2] = v[1].x;
-    e[3] = v[1].y;
+    M *e = t + (lane >> 2) * kTabRow + (lane & 3u) * 4;
+    if constexpr (sizeof(M) == 8) {
+        e[0] = (uint64_t)tb[0].x | ((uint64_t)tb[0].y << 32);
+        e[1] = (uint64_t)tb[0].z | ((uint64_t)tb[0].w << 32);
+        e[2] = (uint64_t)tb[1].x | ((uint64_t)tb[1].y << 32);
+        e[3] = (uint64_t)tb[1].z | ((uint64_t)tb[1].w << 32);
+    } else {
+        e[0] = tb[0].x;
+        e[1] = tb[0].y;
+        e[2] = tb[0].z;
+        e[3] = tb[0].w;
+    }
 }
 
 // One tile: its wavefronts walk their tasks, OR-ing labels into the row
-// block's accumulators lds[0 .. kRowBlock), which hold the tile's labels when
-// it returns (after a workgroup barrier).  Tg + w * tg_stride holds the 256
-// nibble-table entries of word w.
-template <int WAVES>
+// block's accumulators (M)lds[0 .. kRowBlock), which hold the tile's labels
+// when it returns (after a workgroup barrier).  Tg + w * tg_stride holds the
+// 256 nibble-table entries of word w.  M is the label mask: uint64_t for up
+// to 64 propositions, uint32_t for up to 32 (half the table and accumulator
+// bytes, half the LDS bytes per lookup).
+template <int WAVES, typename M>
 __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_tasks,
                                                 const SpRound *__restrict__ rounds,
                                                 const uint16_t *__restrict__ sp_row,
-                                                const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg,
-                                                uint64_t tg_stride, uint64_t *lds)
+                                                const uint64_t *__restrict__ sp_val, const M *__restrict__ Tg,
+                                                uint64_t tg_stride, void *lds)
 {
     const uint32_t lane = threadIdx.x & 63;
     // uniform across the wavefront: task fields and round records become
     // scalars and the per-round branches scalar branches
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t *acc = lds;                                  // kRowBlock accumulators
-    uint64_t *tab = lds + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
+    M *acc = static_cast<M *>(lds);                       // kRowBlock accumulators
+    M *tab = acc + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
     // Every array read here is device memory.  The batch path takes these
     // pointers from its descriptors in memory, where the compiler cannot see
     // their address space: without the casts it would issue flat loads,
@@ -264,7 +285,8 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
     typedef __attribute__((address_space(1))) const uint32_t gu32;
     typedef __attribute__((address_space(1))) const uint16_t gu16;
     typedef __attribute__((address_space(1))) const uint64_t gu64;
-    typedef __attribute__((address_space(1))) const v2u64 gu128;
+    typedef __attribute__((address_space(1))) const v4u32 gu128;
+    constexpr uint32_t kTbN = kTbDwords<M> / 4;  // 16-byte loads of table data per lane
     const gu32 *task = (const gu32 *)(wg_tasks + wave);
     const uint64_t tk_lo = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)task[0]) |
                            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)task[1]) << 32);
@@ -279,7 +301,7 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
             uint32_t meta;
             uint64_t x;        // this lane's word value
             uint16_t r;        // its local row
-            v2u64 tb[2];       // this lane's 32 bytes of the table the round builds
+            v4u32 tb[kTbN];    // this lane's 32 (or 16) bytes of the table the round builds
         };
         // kStages rounds are in flight: round i is fetched (its entries and
         // table data loaded) kStages - 1 rounds before it is processed, and
@@ -306,25 +328,25 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
             st.rec = load_rec(i + kStages);
             st.x = (val_t + e_off)[lane];
             st.r = (row_t + e_off)[lane];
-            // a round that builds no table loads one 32-byte line for the whole
+            // a round that builds no table loads one line for the whole
             // wavefront (still unconditionally): the 2 KiB of its last table
             // would mostly come from L2, the 16 wavefronts' last tables
             // filling the CU's L1
             const gu128 *src = (const gu128 *)(Tg + (uint64_t)tword * tg_stride);
-            const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? 2 * lane : 0u;
-            st.tb[0] = src[tl];
-            st.tb[1] = src[tl + 1];
+            const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? kTbN * lane : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < kTbN; ++k) st.tb[k] = src[tl + k];
         };
 
         // the two slot addresses live in vector registers for the whole walk
         uint32_t slot_a, slot_b;
         asm("v_mov_b32 %0, %1" : "=v"(slot_a) : "s"(lds_addr(tab)));
-        asm("v_mov_b32 %0, %1" : "=v"(slot_b) : "s"(lds_addr(tab) + kTabWords * 8));
+        asm("v_mov_b32 %0, %1" : "=v"(slot_b) : "s"(lds_addr(tab) + kTabWords * (uint32_t)sizeof(M)));
         auto process = [&](const Stage &st) {
             const uint32_t meta = st.meta;
             const uint32_t s0 = (meta & kMetaSlot0) ? 1u : 0u;
             if (meta & (kMetaBuild0 | kMetaBuild1))
-                copy_tables(st.tb, tab + (s0 ^ ((meta & kMetaBuild1) ? 1u : 0u)) * kTabWords, lane);
+                copy_tables<M>(st.tb, tab + (s0 ^ ((meta & kMetaBuild1) ? 1u : 0u)) * kTabWords, lane);
             // LDS instructions of a wavefront complete in issue order, so the
             // lookups below see the whole table; the barrier only stops the
             // compiler from moving LDS accesses across this point.
@@ -338,32 +360,37 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
                 // every lane looks up its word value (an address inside the
                 // slot whatever the value); lanes outside [lane_lo, lane_hi)
                 // then drop their result, which costs less than a branch.
-                // Byte k of ev (od) is 8 x nibble 2k (2k + 1) of the word
-                // value: the byte offset of its entry in the table row
-                const uint64_t m = 0x7878787878787878ull;
-                const uint64_t ev = (st.x << 3) & m, od = (st.x >> 1) & m;
+                // Byte k of ev (od) is sizeof(M) x nibble 2k (2k + 1) of the
+                // word value: the byte offset of its entry in the table row
+                constexpr uint32_t sh = sizeof(M) == 8 ? 3 : 2;
+                const uint64_t m = 0x0F0F0F0F0F0F0F0Full << sh;
+                const uint64_t ev = (st.x << sh) & m, od = (st.x >> (4 - sh)) & m;
                 const uint32_t e[2] = {(uint32_t)ev, (uint32_t)(ev >> 32)};
                 const uint32_t o[2] = {(uint32_t)od, (uint32_t)(od >> 32)};
                 // all sixteen reads are issued before the first result is used
-                uint64_t q[16];
+                M q[16];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    q[8 * h + 0] = lds_entry(add_byte<0>(tb, e[h]), 8 * h + 0);
-                    q[8 * h + 1] = lds_entry(add_byte<0>(tb, o[h]), 8 * h + 1);
-                    q[8 * h + 2] = lds_entry(add_byte<1>(tb, e[h]), 8 * h + 2);
-                    q[8 * h + 3] = lds_entry(add_byte<1>(tb, o[h]), 8 * h + 3);
-                    q[8 * h + 4] = lds_entry(add_byte<2>(tb, e[h]), 8 * h + 4);
-                    q[8 * h + 5] = lds_entry(add_byte<2>(tb, o[h]), 8 * h + 5);
-                    q[8 * h + 6] = lds_entry(add_byte<3>(tb, e[h]), 8 * h + 6);
-                    q[8 * h + 7] = lds_entry(add_byte<3>(tb, o[h]), 8 * h + 7);
+                    q[8 * h + 0] = lds_entry<M>(add_byte<0>(tb, e[h]), 8 * h + 0);
+                    q[8 * h + 1] = lds_entry<M>(add_byte<0>(tb, o[h]), 8 * h + 1);
+                    q[8 * h + 2] = lds_entry<M>(add_byte<1>(tb, e[h]), 8 * h + 2);
+                    q[8 * h + 3] = lds_entry<M>(add_byte<1>(tb, o[h]), 8 * h + 3);
+                    q[8 * h + 4] = lds_entry<M>(add_byte<2>(tb, e[h]), 8 * h + 4);
+                    q[8 * h + 5] = lds_entry<M>(add_byte<2>(tb, o[h]), 8 * h + 5);
+                    q[8 * h + 6] = lds_entry<M>(add_byte<3>(tb, e[h]), 8 * h + 6);
+                    q[8 * h + 7] = lds_entry<M>(add_byte<3>(tb, o[h]), 8 * h + 7);
                 }
                 __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);  // the sixteen LDS reads first
-                uint64_t a = 0;
+                M a = 0;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) a |= q[k];
                 const uint64_t below_hi = lane_hi >= 64 ? ~0ull : ((1ull << lane_hi) - 1ull);
                 const uint64_t act = below_hi & (~0ull << lane_lo);
-                a = ((uint64_t)select_by_lane(act, 0u, (uint32_t)(a >> 32)) << 32) | select_by_lane(act, 0u, (uint32_t)a);
+                if constexpr (sizeof(M) == 8)
+                    a = ((uint64_t)select_by_lane(act, 0u, (uint32_t)(a >> 32)) << 32) |
+                        select_by_lane(act, 0u, (uint32_t)a);
+                else
+                    a = select_by_lane(act, 0u, a);
                 // zero results are skipped: an OR of zero still costs LDS time
                 if (a) __hip_atomic_fetch_or(acc + st.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -371,7 +398,9 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
             // the table data counts as used here even when no table was
             // built, so that its registers are not reused while its loads are
             // in flight (which would make the next fetch wait for every load)
-            asm volatile("" ::"v"(st.tb[0].x), "v"(st.tb[0].y), "v"(st.tb[1].x), "v"(st.tb[1].y));
+#pragma unroll
+            for (uint32_t k = 0; k < kTbN; ++k)
+                asm volatile("" ::"v"(st.tb[k].x), "v"(st.tb[k].y), "v"(st.tb[k].z), "v"(st.tb[k].w));
         };
 
         // the stages in rotation.  When n is not a multiple of kStages the
@@ -388,8 +417,8 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
 #pragma unroll
             for (int k = 0; k + 1 < kStages; ++k) fetch(st[k], k);
         }
-        for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES)
-            reinterpret_cast<ulonglong2 *>(acc)[i] = make_ulonglong2(0ull, 0ull);
+        for (uint32_t i = threadIdx.x; i < kRowBlock * sizeof(M) / 16; i += 64 * WAVES)
+            reinterpret_cast<v4u32 *>(acc)[i] = v4u32{0u, 0u, 0u, 0u};
         __syncthreads();
         for (uint32_t i = 0; i < n; i += kStages) {
 #pragma unroll
@@ -406,20 +435,22 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
 // Pt[0 .. kRowBlock), or (compact) only the n_slot rows slot_row[..] it
 // touches at Pt[0 .. n_slot).  Streaming stores: the partials are read once,
 // by the combine kernel.
-template <int WAVES>
-__device__ __forceinline__ void write_partials(const uint64_t *acc, uint64_t *__restrict__ Pt)
+template <int WAVES, typename M>
+__device__ __forceinline__ void write_partials(const void *lds, M *Pt)
 {
-    for (uint32_t i = threadIdx.x; i < kRowBlock / 2; i += 64 * WAVES) {
-        const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(acc)[i];
-        __builtin_nontemporal_store(v.x, Pt + 2 * i);
-        __builtin_nontemporal_store(v.y, Pt + 2 * i + 1);
-    }
+    // device memory (the batch's pointer comes from its descriptors)
+    typedef __attribute__((address_space(1))) v4u32 gv4;
+    const v4u32 *acc = static_cast<const v4u32 *>(lds);
+    gv4 *dst = (gv4 *)Pt;
+    for (uint32_t i = threadIdx.x; i < kRowBlock * sizeof(M) / 16; i += 64 * WAVES)
+        __builtin_nontemporal_store(acc[i], dst + i);
 }
 
-template <int WAVES>
-__device__ __forceinline__ void write_partials_compact(const uint64_t *acc, uint64_t *__restrict__ Pt,
+template <int WAVES, typename M>
+__device__ __forceinline__ void write_partials_compact(const void *lds, M *__restrict__ Pt,
                                                        const uint16_t *__restrict__ slot_row, uint32_t n_slot)
 {
+    const M *acc = static_cast<const M *>(lds);
     for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES)
         __builtin_nontemporal_store(acc[slot_row[k]], Pt + k);
 }
@@ -427,34 +458,36 @@ __device__ __forceinline__ void write_partials_compact(const uint64_t *acc, uint
 // One workgroup per tile of a single frame: workgroup b runs tile
 // block_tile[b], whose tasks tasks_launch holds at b * WAVES (no dependent
 // load before the first task).  Partials P[tile][kRowBlock].
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES)
+// With 32-bit masks a workgroup takes half the LDS, and two share a CU.
+template <int WAVES, typename M>
+__global__ void __launch_bounds__(64 * WAVES, sizeof(M) == 8 ? 1 : 2)
 k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict__ tasks_launch,
               const SpRound *__restrict__ rounds, const uint16_t *__restrict__ sp_row,
-              const uint64_t *__restrict__ sp_val, const uint64_t *__restrict__ Tg, uint64_t *__restrict__ P,
+              const uint64_t *__restrict__ sp_val, const M *__restrict__ Tg, M *__restrict__ P,
               const uint32_t *__restrict__ tile_slot, const uint16_t *__restrict__ slot_row)
 {
     extern __shared__ uint64_t lds[];
     const uint32_t tile = block_tile[blockIdx.x];
-    tile_accumulate<WAVES>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256, lds);
+    tile_accumulate<WAVES, M>(tasks_launch + (uint64_t)blockIdx.x * WAVES, rounds, sp_row, sp_val, Tg, 256, lds);
     if (tile_slot) {
         const uint32_t s0 = tile_slot[tile], s1 = tile_slot[tile + 1];
-        write_partials_compact<WAVES>(lds, P + s0, slot_row + s0, s1 - s0);
+        write_partials_compact<WAVES, M>(lds, P + s0, slot_row + s0, s1 - s0);
     } else {
-        write_partials<WAVES>(lds, P + (uint64_t)tile * kRowBlock);
+        write_partials<WAVES, M>(lds, P + (uint64_t)tile * kRowBlock);
     }
 }
 
 // OR of row t's compact partials: slots row_slots[row_slot_off[t] ..
 // row_slot_off[t + 1]), four loads in flight (indices past the last slot read
 // it again, which leaves the OR unchanged; a row no tile touches has none).
-__device__ __forceinline__ uint64_t row_slots_or(const uint64_t *__restrict__ P, const uint32_t *__restrict__ off,
+template <typename M>
+__device__ __forceinline__ uint64_t row_slots_or(const M *__restrict__ P, const uint32_t *__restrict__ off,
                                                  const uint32_t *__restrict__ slots, uint64_t t)
 {
     const uint32_t k0 = off[t], k1 = off[t + 1];
     uint64_t bits = 0;
     for (uint32_t kb = k0; kb < k1; kb += 4) {
-        uint64_t v[4];
+        M v[4];
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j) v[j] = P[slots[min(kb + j, k1 - 1)]];
 #pragma unroll
@@ -570,12 +603,12 @@ template <int WAVES>
 __device__ __forceinline__ void batch_tile(const GroupDesc *__restrict__ groups, const TileItem &it, uint64_t *lds)
 {
     const GroupDesc &g = groups[it.group];
-    tile_accumulate<WAVES>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
-                           g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256, lds);
+    tile_accumulate<WAVES, uint64_t>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
+                                     g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256, lds);
     if (g.fused)
         emit_tile<WAVES>(lds, g, it.gi, it.tile);
     else
-        write_partials<WAVES>(lds, g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock);
+        write_partials<WAVES, uint64_t>(lds, g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock);
 }
 
 // One workgroup per tile item: workgroup b runs items[launch[b]].
@@ -742,12 +775,13 @@ k_pack_batch_tables(const GroupDesc *__restrict__ groups, const PackItem *__rest
 }
 
 // OR of row t's partials over the tiles of its row block.
-__device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile,
+template <typename M>
+__device__ __forceinline__ uint64_t row_partials(const M *__restrict__ P, const uint32_t *__restrict__ rb_tile,
                                                  uint64_t t)
 {
     // device memory (the batch passes pointers read from its descriptors:
     // without the casts they would be flat loads)
-    const __attribute__((address_space(1))) uint64_t *Pg = (const __attribute__((address_space(1))) uint64_t *)P;
+    const __attribute__((address_space(1))) M *Pg = (const __attribute__((address_space(1))) M *)P;
     const __attribute__((address_space(1))) uint32_t *rbt = (const __attribute__((address_space(1))) uint32_t *)rb_tile;
     const uint64_t rb = t / kRowBlock, loc = t % kRowBlock;
     const uint32_t k0 = rbt[rb], k1 = rbt[rb + 1];
@@ -755,7 +789,7 @@ __device__ __forceinline__ uint64_t row_partials(const uint64_t *__restrict__ P,
     // sixteen loads in flight at a time: indices past the block's last tile
     // read that tile again, which leaves the OR unchanged
     for (uint32_t kb = k0; kb < k1; kb += 16) {
-        uint64_t v[16];
+        M v[16];
 #pragma unroll
         for (uint32_t j = 0; j < 16; ++j) v[j] = Pg[(uint64_t)min(kb + j, k1 - 1) * kRowBlock + loc];
 #pragma unroll
@@ -801,8 +835,9 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
 // ... of the block's n_props * 64 bytes, fetching the bits of each unit's row
 // from the lane that holds them; otherwise the block is staged in LDS and
 // written by emit_block.
+template <typename M>
 __global__ void __launch_bounds__(256)
-k_combine(const uint64_t *__restrict__ P, const uint32_t *__restrict__ rb_tile,
+k_combine(const M *__restrict__ P, const uint32_t *__restrict__ rb_tile,
           const uint32_t *__restrict__ row_slot_off, const uint32_t *__restrict__ row_slots, uint64_t n_traj,
           uint32_t n_props, uint8_t *__restrict__ L)
 {
@@ -1338,25 +1373,29 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
         sp->n_used = W;
     }
     // tile workgroups use more than 64 KB of LDS
-    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles<kTileWaves>),
+    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles<kTileWaves, uint64_t>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
+    LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles<kTileWaves, uint32_t>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds32));
     LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles_batch<kTileWaves>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
     LBL_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_label_tiles_queue<kTileWaves>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLds));
     const uint32_t n_cu = (uint32_t)device_cu_count();
-    sp->tilings.resize(1 + kBatchTilings);
+    sp->tilings.resize(kNarrowTiling + 1);
     std::vector<uint16_t> rows_host(nnz);
     if (nnz) LBL_HIP_TRY(hipMemcpy(rows_host.data(), sp->row, nnz * sizeof(uint16_t), hipMemcpyDeviceToHost));
-    for (int i = 0; i <= kBatchTilings; ++i) {
-        std::vector<uint32_t> k = i == 0 ? choose_tiles(block_costs(seg_start, rb_seg), n_cu)
-                                         : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
+    for (int i = 0; i <= kNarrowTiling; ++i) {
+        // the 32-bit mask kernel runs two tile workgroups per CU
+        const bool one_frame = i == 0 || i == kNarrowTiling;
+        std::vector<uint32_t> k = one_frame ? choose_tiles(block_costs(seg_start, rb_seg), i == 0 ? n_cu : 2 * n_cu)
+                                            : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
         TilingHost h;
         make_tiling(seg_start, seg_word, rb_seg, k, &h);
         lbl_status st = upload_tiling(h, &sp->tilings[i], &sp->round_bytes);
         if (st != LBL_OK) return st;
         CompactHost c;
-        if (i == 0 && make_compact(h, rows_host, seg_start, rb_seg, a->n_traj, &c)) {
+        if (one_frame && make_compact(h, rows_host, seg_start, rb_seg, a->n_traj, &c)) {
             st = upload_compact(c, &sp->tilings[i], &sp->round_bytes);
             if (st != LBL_OK) return st;
         }
@@ -1377,40 +1416,61 @@ lbl_status build_sparse(lbl_abs *a)
 
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)
 {
-    const SpTiling &tl = a->sp->tilings[t];
-    const size_t partials = tl.tile_slot && n_lane_groups == 1 ? (size_t)tl.n_slots
-                                                                : (size_t)n_lane_groups * tl.n_tiles * kRowBlock;
-    return up256((size_t)a->n_words * 256 * n_lane_groups * sizeof(uint64_t)) + partials * sizeof(uint64_t);
+    auto bytes = [&](int ti, size_t mask) {
+        const SpTiling &tl = a->sp->tilings[ti];
+        const size_t partials = tl.tile_slot && n_lane_groups == 1 ? (size_t)tl.n_slots
+                                                                    : (size_t)n_lane_groups * tl.n_tiles * kRowBlock;
+        return up256((size_t)a->n_words * 256 * n_lane_groups * mask) + partials * mask;
+    };
+    size_t b = bytes(t, sizeof(uint64_t));
+    if (t == 0 && n_lane_groups == 1 && (int)a->sp->tilings.size() > kNarrowTiling)
+        b = std::max(b, bytes(kNarrowTiling, sizeof(uint32_t)));
+    return b;
 }
+
+namespace {
+
+// The three kernels of one frame with M-bit masks on tiling tl.
+template <typename M>
+lbl_status run_swm_t(const lbl_abs *a, const SpTiling &tl, size_t lds, const uint8_t *O, uint32_t n_props, void *ws,
+                     uint8_t *L, hipStream_t s, bool spans)
+{
+    const SparseLayout &sp = *a->sp;
+    M *Tg = static_cast<M *>(ws);
+    M *P = Tg + up256((size_t)a->n_words * 256 * sizeof(M)) / sizeof(M);
+    auto span_begin = [&](hipStream_t st) { return spans ? lbl::span_begin(st) : nullptr; };
+    auto span_end = [&](void *b, hipStream_t st, int kind) {
+        if (spans) lbl::span_end(b, st, kind);
+    };
+    void *spn = span_begin(s);
+    hipLaunchKernelGGL(k_pack_tables<M>, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
+                       n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
+    LBL_HIP_TRY(hipGetLastError());
+    span_end(spn, s, 0);
+    spn = span_begin(s);
+    hipLaunchKernelGGL((k_label_tiles<kTileWaves, M>), dim3(tl.n_tiles), dim3(64 * kTileWaves), lds, s,
+                       tl.block_tile, tl.tasks_launch, tl.rounds, sp.row, sp.val, Tg, P, tl.tile_slot, tl.slot_row);
+    LBL_HIP_TRY(hipGetLastError());
+    span_end(spn, s, 1);
+    spn = span_begin(s);
+    hipLaunchKernelGGL(k_combine<M>, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile,
+                       tl.row_slot_off, tl.row_slots, a->n_traj, n_props, L);
+    LBL_HIP_TRY(hipGetLastError());
+    span_end(spn, s, 3);
+    return LBL_OK;
+}
+
+}  // namespace
 
 lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L, hipStream_t s,
                    bool spans)
 {
     LBL_REQUIRE(a->sp != nullptr, "the abstraction has no sparse layout");
     const SparseLayout &sp = *a->sp;
-    const SpTiling &tl = sp.tilings[0];
-    uint64_t *Tg = static_cast<uint64_t *>(ws);
-    uint64_t *P = Tg + up256((size_t)a->n_words * 256 * sizeof(uint64_t)) / sizeof(uint64_t);
-    auto span_begin = [&](hipStream_t st) { return spans ? lbl::span_begin(st) : nullptr; };
-    auto span_end = [&](void *b, hipStream_t st, int kind) {
-        if (spans) lbl::span_end(b, st, kind);
-    };
-    void *spn = span_begin(s);
-    hipLaunchKernelGGL(k_pack_tables, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
-    LBL_HIP_TRY(hipGetLastError());
-    span_end(spn, s, 0);
-    spn = span_begin(s);
-    hipLaunchKernelGGL(k_label_tiles<kTileWaves>, dim3(tl.n_tiles), dim3(64 * kTileWaves), kTileLds, s, tl.block_tile,
-                       tl.tasks_launch, tl.rounds, sp.row, sp.val, Tg, P, tl.tile_slot, tl.slot_row);
-    LBL_HIP_TRY(hipGetLastError());
-    span_end(spn, s, 1);
-    spn = span_begin(s);
-    hipLaunchKernelGGL(k_combine, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile,
-                       tl.row_slot_off, tl.row_slots, a->n_traj, n_props, L);
-    LBL_HIP_TRY(hipGetLastError());
-    span_end(spn, s, 3);
-    return LBL_OK;
+    // frames of at most 32 propositions take the 32-bit mask kernels
+    if (n_props <= 32 && (int)sp.tilings.size() > kNarrowTiling)
+        return run_swm_t<uint32_t>(a, sp.tilings[kNarrowTiling], kTileLds32, O, n_props, ws, L, s, spans);
+    return run_swm_t<uint64_t>(a, sp.tilings[0], kTileLds, O, n_props, ws, L, s, spans);
 }
 
 }  // namespace lbl

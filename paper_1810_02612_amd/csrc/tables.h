@@ -65,4 +65,23 @@ __device__ __forceinline__ void write_tables(uint64_t cell, uint64_t *dst, uint3
     d[1] = make_ulonglong2(h | o1, h | o0 | o1);
 }
 
+// 32-bit version of quad_bcast.
+template <int C>
+__device__ __forceinline__ uint32_t quad_bcast32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, C * 0x55, 0xF, 0xF, false);
+}
+
+// write_tables for 32-bit proposition masks (frames of at most 32
+// propositions): the same 16 x 16 tables with 4-byte entries, lane 4n + j
+// writing the 16 bytes of entries [n][4j .. 4j+3] to dst[n * 16 + 4j ..].
+__device__ __forceinline__ void write_tables32(uint32_t cell, uint32_t *dst, uint32_t lane)
+{
+    const uint32_t o0 = quad_bcast32<0>(cell), o1 = quad_bcast32<1>(cell);
+    const uint32_t o2 = quad_bcast32<2>(cell), o3 = quad_bcast32<3>(cell);
+    const uint32_t j = lane & 3u;
+    const uint32_t h = ((j & 1u) ? o2 : 0u) | ((j & 2u) ? o3 : 0u);
+    *reinterpret_cast<uint4 *>(dst + (lane >> 2) * 16 + 4 * j) = make_uint4(h, h | o0, h | o1, h | o0 | o1);
+}
+
 }  // namespace lbl

@@ -61,7 +61,8 @@ class AbsInfo(ctypes.Structure):
                 ("int8_bytes", ctypes.c_uint64), ("nonzero_words", ctypes.c_uint64), ("set_cells", ctypes.c_uint64),
                 ("sparse_entries", ctypes.c_uint64), ("sparse_bytes", ctypes.c_uint64),
                 ("sparse_frame_bytes", ctypes.c_uint64), ("sparse_tiles", ctypes.c_uint32),
-                ("sparse_row_block", ctypes.c_uint32)]
+                ("sparse_row_block", ctypes.c_uint32), ("sparse_frame_bytes_narrow", ctypes.c_uint64),
+                ("sparse_tiles_narrow", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
