@@ -55,6 +55,18 @@ struct SpRound {
 };
 constexpr uint32_t kMetaBuild0 = 1u << 24, kMetaBuild1 = 1u << 25, kMetaSlot0 = 1u << 26;
 
+// One chunk of a tile for the direct-mask kernel (frames of at most 4
+// propositions): up to 64 consecutive entries, lane l taking entry
+// chunk start + l.  Bit i of `starts` is set iff entry i + 1 of the chunk
+// begins a new segment, so lane l's segment is seg0 (that of entry 0,
+// counted from the tile's first segment) plus the popcount of the bits below
+// l.  Lanes at or past n_valid hold no entry of the tile.
+struct SpChunk {
+    uint64_t starts;
+    uint32_t seg0;
+    uint32_t n_valid;
+};
+
 // A split of the layout into tiles: kTileWaves tasks per tile, every tile in
 // one row block; rb_tile[rb] .. rb_tile[rb + 1] are the tiles of block rb.
 struct SpTiling {
@@ -76,6 +88,18 @@ struct SpTiling {
     uint16_t *slot_row = nullptr;      // device [n_slots]
     uint32_t *row_slot_off = nullptr;  // device [n_traj + 1]
     uint32_t *row_slots = nullptr;     // device [n_slots]
+    // Chunks of the tiles for the direct-mask kernel (the narrow tiling
+    // only, null otherwise): tile t's entries begin at tile_e0[t] and are the
+    // chunks tile_chunk[t] .. tile_chunk[t + 1], 64 entries apart; its
+    // segments are tile_seg[2 t] .. + tile_seg[2 t + 1] (at most
+    // max_tile_segs), with words seg_word[..].
+    uint64_t n_chunks = 0;
+    uint32_t max_tile_segs = 0;
+    uint64_t *tile_e0 = nullptr;      // device [n_tiles]
+    uint32_t *tile_chunk = nullptr;   // device [n_tiles + 1]
+    uint32_t *tile_seg = nullptr;     // device [2 n_tiles]
+    SpChunk *chunks = nullptr;        // device [n_chunks]
+    uint32_t *seg_word = nullptr;     // device [segments]
 };
 
 // XCDs of an MI355X.  Workgroup b of a launch runs on XCD b % kXcds, and
@@ -170,6 +194,17 @@ struct CompactHost {
 };
 bool make_compact(const TilingHost &h, const std::vector<uint16_t> &row, const std::vector<uint64_t> &seg_start,
                   const std::vector<uint64_t> &rb_seg, uint64_t n_traj, CompactHost *out);
+// Chunks of a tiling's tiles (host); tile t covers entries
+// [tasks[t * kTileWaves].lo, the next tile's first entry or its row block's
+// end) and the segments holding them.
+struct ChunkHost {
+    std::vector<uint64_t> tile_e0;
+    std::vector<uint32_t> tile_chunk;
+    std::vector<uint32_t> tile_seg;  // first segment, count
+    std::vector<SpChunk> chunks;
+};
+void make_chunks(const TilingHost &h, const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
+                 ChunkHost *out);
 // Cost of walking each row block's entries in rounds.
 std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg);
 // Tiles per row block (at least one each) for `target` tiles in total of

@@ -184,6 +184,8 @@ def test_cfg3_full_size_whole_L(cfg3_full, rho):
 @pytest.mark.parametrize("nx,ny,n_traj,n_props", [
     (8, 8, 1, 1), (8, 8, 3, 64), (24, 8, 65, 7), (24, 40, 130, 17), (64, 64, 1007, 33),
     (40, 24, 257, 63), (136, 8, 33, 16), (8, 136, 77, 2),
+    # three and four propositions (direct per-word masks), two row blocks
+    (24, 24, 8300, 3), (56, 8, 700, 4),
     # 48 and 32 columns (three and two 16-byte units per row), 8257 rows: two
     # row blocks of the sparse layout, the second one 65 rows long
     (16, 16, 8257, 48), (32, 16, 130, 32),
@@ -275,6 +277,10 @@ def test_morton_cell_ids_give_the_row_major_labels(cfg, cfg1, cfg2):
         for name, k in KERNELS.items():
             say(f"morton cfg{cfg} kernel {name}")
             assert_same(label(h, Oz, a.n_traj, k), want, f"morton/cfg{cfg}/{name}")
+        for p in (1, 2, 3, 4):
+            say(f"morton cfg{cfg} sparse kernel, first {p} propositions")
+            assert_same(label(h, np.ascontiguousarray(Oz[:, :p]), a.n_traj, lbl.KERNEL_SPARSE), want[:, :p],
+                        f"morton/cfg{cfg}/{p} props")
     finally:
         lbl.free_abstraction(h)
     if cfg == 1:
