@@ -117,7 +117,7 @@ def traffic_from_profile(kernel_file: str, summary: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: float) -> dict:
+def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: float, issued_ops=None) -> dict:
     """Roofline of one labeling launch from its algorithmic bytes or ops.
 
     bits    : dense bitpacked T (8 B per 64-cell word of every row) + packed
@@ -126,18 +126,25 @@ def roofline(kernel: str, info: dict, n_traj: int, n_props: int, kernel_ms: floa
               tiling's task and round tables) + cell masks (W x 64 x 8 B)
               + label bits (8 B per row)                              -> HBM
               (frames of at most 32 propositions: their own tiling's
-              tables, 4 B cell masks and 4 B of label bits per row)
-    mfma    : 2 N_t N_c N_p int8 multiply-adds                         -> MFMA
+              tables, 4 B cell masks and 4 B of label bits per row;
+              frames of at most 4: the direct-mask kernel's entries, chunk,
+              part and tile records, one bit per cell and proposition of
+              frame data, and L itself, which that kernel writes)
+    mfma    : the int8 multiply-adds the kernel issues (issued_ops, the
+              blocks it does not skip), else the dense 2 N_t N_c N_p  -> MFMA
     mfma_i8 : int8 T (1 B per cell of every row) + masks + L           -> HBM
     """
     W = info["n_words"]
     t = kernel_ms * 1e-3
     if kernel == "mfma":
-        ops = 2.0 * n_traj * W * 64 * n_props
+        dense = 2.0 * n_traj * W * 64 * n_props
+        ops = float(issued_ops) if issued_ops is not None else dense
         return {"bound": "mfma", "achieved": ops / t / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": ops / t / 1e12 / INT8_PEAK_TOPS, "traffic": None, "kernel": "label_mfma",
-                "kernel_ms": kernel_ms, "algorithmic_ops": ops}
-    if kernel == "sparse" and n_props <= 32 and info.get("sparse_frame_bytes_narrow"):
+                "kernel_ms": kernel_ms, "algorithmic_ops": ops, "dense_equivalent_ops": dense}
+    if kernel == "sparse" and n_props <= 4 and info.get("sparse_frame_bytes_direct"):
+        alg, src, summary = info["sparse_frame_bytes_direct"] + W * 8 * n_props + n_traj * n_props, "sparse.hip", None
+    elif kernel == "sparse" and n_props <= 32 and info.get("sparse_frame_bytes_narrow"):
         alg, src, summary = info["sparse_frame_bytes_narrow"] + W * 64 * 4 + n_traj * 4, "sparse.hip", None
     elif kernel == "sparse":
         alg, src, summary = info["sparse_frame_bytes"] + W * 64 * 8 + n_traj * 8, "sparse.hip", "label_sparse_200k_512_64_traffic.json"
@@ -593,8 +600,9 @@ def main():
     pack_ms = prof["pack_ms"] / max(1, prof["pack_launches"])
     emit_ms = prof["emit_ms"] / max(1, prof["emit_launches"]) if prof["emit_launches"] else 0.0
     W = info["n_words"]
-    kernel = plan.split("-> ")[-1].split("(")[0]
-    roof = roofline(kernel, info, a.n_traj, n_props, label_ms)
+    kernel = plan.split("-> ")[-1].split("(")[0] if args.kernel == "auto" else args.kernel
+    roof = roofline(kernel, info, a.n_traj, n_props, label_ms,
+                    issued_ops=mfma_issued_ops(lbl, a, n_props) if kernel == "mfma" else None)
     log(f"step {ms_per_step:.3f} ms, label kernel {label_ms:.4f} ms, pack {pack_ms:.4f} ms, emit {emit_ms:.4f} ms, "
         f"{roof['achieved']:.0f} {roof['unit']} ({100 * roof['frac']:.1f}%)")
 
@@ -697,17 +705,15 @@ def main():
                 lbl.label_frame(h8, Ox[0], n_props, L, flags=kf, stream=stream)
                 w, pr = timed_steps(lbl, torch, h8, Ox, n_props, L, kf, args.sweep_steps, stream)
                 kms = pr["label_ms"] / max(1, pr["label_launches"])
-                r = roofline(name, info8, a.n_traj, n_props, kms)
+                # MFMA: only the blocks the kernel multiplies count, not the
+                # dense 2 N_t N_c N_p of the product
+                r = roofline(name, info8, a.n_traj, n_props, kms, issued_ops=mfma_ops if name == "mfma" else None)
                 row = {"rho": rho, "kernel": name, "kernel_ms": kms, "step_ms": 1000 * w / args.sweep_steps,
                        "label_kernel_pairs_per_s": pairs / (kms * 1e-3), "roofline_bound": r["bound"],
                        "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
                 if name == "mfma":
-                    # only the blocks the kernel multiplies count, not the dense
-                    # 2 N_t N_c N_p of the product
-                    row["achieved"] = mfma_ops / (kms * 1e-3) / 1e12
-                    row["frac"] = row["achieved"] / INT8_PEAK_TOPS
                     row["issued_ops"] = mfma_ops
-                    row["dense_equivalent_ops"] = r["algorithmic_ops"]
+                    row["dense_equivalent_ops"] = r["dense_equivalent_ops"]
                 # step_ms is taken with per-kernel events on, so it includes their cost
                 sweep.append(row)
                 log("sweep", sweep[-1])

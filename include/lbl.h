@@ -171,7 +171,12 @@ typedef struct {
                                            most 32 propositions (their own
                                            tiling, 32-bit label masks) */
     uint32_t sparse_tiles_narrow;       /* workgroups of such a launch */
-    uint32_t reserved;                  /* 0 */
+    uint32_t sparse_tiles_direct;       /* workgroups of the direct-mask launch
+                                           (frames of at most 4 propositions;
+                                           0 when that kernel is not built) */
+    uint64_t sparse_frame_bytes_direct; /* bytes that launch reads from the
+                                           layout: every entry, its chunk, part
+                                           and tile records */
 } lbl_abs_info;
 
 lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out);

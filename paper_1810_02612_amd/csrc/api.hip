@@ -420,7 +420,8 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
     out->sparse_row_block = 0;
     out->sparse_frame_bytes_narrow = 0;
     out->sparse_tiles_narrow = 0;
-    out->reserved = 0;
+    out->sparse_tiles_direct = 0;
+    out->sparse_frame_bytes_direct = 0;
     if (a->sp) {
         const SparseLayout &sp = *a->sp;
         const SpTiling &t = sp.tilings[0];
@@ -438,6 +439,12 @@ lbl_status lbl_abstraction_info(lbl_abs_t a, lbl_abs_info *out)
             out->sparse_frame_bytes_narrow = entry_bytes + (uint64_t)u.n_tiles * kTileWaves * sizeof(SpTask) +
                                              u.n_rounds * sizeof(SpRound) + u.n_slots * sizeof(uint16_t);
             out->sparse_tiles_narrow = u.n_tiles;
+        }
+        const DirectLayout &d = sp.direct;
+        if (d.chunks) {
+            out->sparse_tiles_direct = d.n_tiles;
+            out->sparse_frame_bytes_direct = entry_bytes + d.n_chunks * sizeof(SpChunk) +
+                                             d.n_parts * sizeof(DirectPart) + (d.n_tiles + 1ull) * sizeof(uint32_t);
         }
     }
     return LBL_OK;

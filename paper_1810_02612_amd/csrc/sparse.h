@@ -55,17 +55,53 @@ struct SpRound {
 };
 constexpr uint32_t kMetaBuild0 = 1u << 24, kMetaBuild1 = 1u << 25, kMetaSlot0 = 1u << 26;
 
-// One chunk of a tile for the direct-mask kernel (frames of at most 4
-// propositions): up to 64 consecutive entries, lane l taking entry
+// One chunk for the direct-mask kernel (frames of at most 4 propositions):
+// up to 64 consecutive entries of one row block, lane l taking entry
 // chunk start + l.  Bit i of `starts` is set iff entry i + 1 of the chunk
 // begins a new segment, so lane l's segment is seg0 (that of entry 0,
-// counted from the tile's first segment) plus the popcount of the bits below
-// l.  Lanes at or past n_valid hold no entry of the tile.
+// counted from its part's first segment) plus the popcount of the bits below
+// l.  Lanes at or past n_valid hold no entry.
 struct SpChunk {
     uint64_t starts;
     uint32_t seg0;
     uint32_t n_valid;
 };
+
+// A part of a direct-mask tile: the tile's chunks [c0, c1) that lie in row
+// block rb, the first of them starting at entry e0; their segments are
+// seg_first .. + n_seg.
+struct DirectPart {
+    uint64_t e0;
+    uint32_t c0, c1;
+    uint32_t rb;
+    uint32_t seg_first, n_seg;
+    uint32_t pad;
+};
+
+// The direct-mask kernel's split of the layout: the chunks of every row
+// block (64 entries from the block's first, the block's last chunk
+// partial), in layout order, cut into n_tiles tiles of equal chunk counts;
+// a tile spanning row blocks has one part per block.  Tile t's parts are
+// tile_part[t] .. tile_part[t + 1].  Empty (no device arrays) when not built.
+struct DirectLayout {
+    uint32_t n_tiles = 0;
+    uint32_t n_parts = 0;
+    uint32_t max_part_segs = 0;
+    uint64_t n_chunks = 0;
+    uint32_t *tile_part = nullptr;  // device [n_tiles + 1]
+    DirectPart *parts = nullptr;    // device
+    SpChunk *chunks = nullptr;      // device [n_chunks]
+    uint32_t *seg_word = nullptr;   // device [segments]
+};
+struct DirectHost {
+    std::vector<uint32_t> tile_part;
+    std::vector<DirectPart> parts;
+    std::vector<SpChunk> chunks;
+};
+// Host: the direct-mask split of a row-block-ordered segment list into
+// n_tiles tiles (see SparseLayout::direct).
+void make_direct(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg, uint32_t n_tiles,
+                 DirectHost *out);
 
 // A split of the layout into tiles: kTileWaves tasks per tile, every tile in
 // one row block; rb_tile[rb] .. rb_tile[rb + 1] are the tiles of block rb.
@@ -88,18 +124,6 @@ struct SpTiling {
     uint16_t *slot_row = nullptr;      // device [n_slots]
     uint32_t *row_slot_off = nullptr;  // device [n_traj + 1]
     uint32_t *row_slots = nullptr;     // device [n_slots]
-    // Chunks of the tiles for the direct-mask kernel (the narrow tiling
-    // only, null otherwise): tile t's entries begin at tile_e0[t] and are the
-    // chunks tile_chunk[t] .. tile_chunk[t + 1], 64 entries apart; its
-    // segments are tile_seg[2 t] .. + tile_seg[2 t + 1] (at most
-    // max_tile_segs), with words seg_word[..].
-    uint64_t n_chunks = 0;
-    uint32_t max_tile_segs = 0;
-    uint64_t *tile_e0 = nullptr;      // device [n_tiles]
-    uint32_t *tile_chunk = nullptr;   // device [n_tiles + 1]
-    uint32_t *tile_seg = nullptr;     // device [2 n_tiles]
-    SpChunk *chunks = nullptr;        // device [n_chunks]
-    uint32_t *seg_word = nullptr;     // device [segments]
 };
 
 // XCDs of an MI355X.  Workgroup b of a launch runs on XCD b % kXcds, and
@@ -119,6 +143,8 @@ struct SparseLayout {
     // tilings[1 + i]: 2^i tiles per row block (batches); tilings[kNarrowTiling]:
     // one frame of at most 32 propositions (about two tiles per CU)
     std::vector<SpTiling> tilings;
+    // the direct-mask kernel's tiles (frames of at most 4 propositions)
+    DirectLayout direct;
     size_t round_bytes = 0;      // device bytes of all tilings' tables
     ~SparseLayout();
 };
@@ -194,17 +220,6 @@ struct CompactHost {
 };
 bool make_compact(const TilingHost &h, const std::vector<uint16_t> &row, const std::vector<uint64_t> &seg_start,
                   const std::vector<uint64_t> &rb_seg, uint64_t n_traj, CompactHost *out);
-// Chunks of a tiling's tiles (host); tile t covers entries
-// [tasks[t * kTileWaves].lo, the next tile's first entry or its row block's
-// end) and the segments holding them.
-struct ChunkHost {
-    std::vector<uint64_t> tile_e0;
-    std::vector<uint32_t> tile_chunk;
-    std::vector<uint32_t> tile_seg;  // first segment, count
-    std::vector<SpChunk> chunks;
-};
-void make_chunks(const TilingHost &h, const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
-                 ChunkHost *out);
 // Cost of walking each row block's entries in rounds.
 std::vector<double> block_costs(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg);
 // Tiles per row block (at least one each) for `target` tiles in total of

@@ -189,12 +189,26 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
 // Frames of at most NP <= 4 propositions: one wavefront per word, lane b
 // holding cell b as in k_pack_tables; the word's NP proposition masks
 // Tm[w * NP + p] (bit b set iff cell b meets proposition p; zero for
-// p >= n_props), lane p writing mask p.
+// p >= n_props), lane p writing mask p.  The grid also zeroes the frame's
+// n_L label bytes at L, which the label kernel then sets where true.
 template <int NP>
 __global__ void __launch_bounds__(256)
 k_pack_masks(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
-             uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tm)
+             uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tm,
+             uint8_t *__restrict__ L, uint64_t n_L)
 {
+    {
+        // L in 16-byte units from its first aligned byte, the ends byte by byte
+        const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        const uint64_t head = min<uint64_t>((16 - (reinterpret_cast<uintptr_t>(L) & 15u)) & 15u, n_L);
+        const uint64_t n16 = (n_L - head) / 16;
+        const uint64_t tail = head + 16 * n16;
+        if (tid < head) L[tid] = 0;
+        if (tid < n_L - tail) L[tail + tid] = 0;
+        v4u32 *body = reinterpret_cast<v4u32 *>(L + head);
+        for (uint64_t i = tid; i < n16; i += stride) body[i] = v4u32{0u, 0u, 0u, 0u};
+    }
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n_items) return;  // whole wavefronts
@@ -504,26 +518,31 @@ k_label_tiles(const uint32_t *__restrict__ block_tile, const SpTask *__restrict_
     }
 }
 
-// Frames of at most NP <= 4 propositions (the direct-mask kernel), on the
-// narrow tiling's tiles and compact partial slots.  A label needs no nibble
-// table here: bit p of an entry's label is (word value AND mask p of its
-// word) != 0, the masks Tm[word * NP + p] written by k_pack_masks.  A tile's
-// entries are a contiguous range, so its segments are too: at the start the
-// workgroup copies the masks of its n_seg segments into LDS (segment-local
-// index i at msk[i * NP]).  It then does not walk the tile by segments: the
-// tile's chunks of 64 entries are dealt to its wavefronts in turn (chunk j
-// to wavefront j % WAVES), so the 16 wavefronts read consecutive 1 KiB
-// pieces of the entry arrays together.  Lane l of a chunk takes entry
-// e0 + 64 j + l, whose segment is the chunk's first plus the start bits
-// below l (a masked bit count); it reads that segment's masks from LDS and
-// ORs its label into the row's 32-bit LDS accumulator.
+// Frames of at most NP <= 4 propositions (the direct-mask kernel).  A label
+// needs no nibble table here: bit p of an entry's label is (word value AND
+// mask p of its word) != 0, with the masks Tm[word * NP + p] written by
+// k_pack_masks.  Nor does a tile walk its entries by segment: the layout's
+// 64-entry chunks are cut into tiles of equal chunk counts (so that tiles
+// take equal time, whatever the row blocks' sizes), and a tile's chunks in
+// one row block (a part) are dealt to its wavefronts in turn (chunk j to
+// wavefront j % WAVES), so that the 16 wavefronts read consecutive 1 KiB
+// pieces of the entry arrays together.  Per part: the masks of the part's
+// segments are copied into LDS (segment i at msk[i * NP]); lane l of a chunk
+// takes entry e0 + 64 j + l, whose segment is the chunk's first plus the
+// start bits below l (a masked bit count), and ORs its label into the row's
+// 32-bit LDS accumulator; then every row of the block with a non-zero
+// accumulator gets a 1 in its label byte for each set bit.  L was zeroed by
+// k_pack_masks, and the tiles sharing a row only ever store 1 into its
+// bytes, so the label bytes need no combine step (concurrent stores of the
+// same value to a byte are benign; stores to neighbouring bytes do not
+// interfere).
 //
-// Only the chunk records and the entries come from memory in the loop, all
-// of them kDirectAhead chunks before they are processed (vector loads
-// complete in issue order, and nothing waits on a later load): every load is
-// unconditional and in bounds (indices clamp to the wavefront's last chunk,
-// the entry arrays carry kEntryPad entries of padding); only the processing
-// of chunks past the last is skipped.
+// Only the chunk records and the entries come from memory in the chunk
+// loop, all of them kDirectAhead chunks before they are processed (vector
+// loads complete in issue order, and nothing waits on a later load): every
+// load is unconditional and in bounds (indices clamp to the wavefront's last
+// chunk of the part, the entry arrays carry kEntryPad entries of padding);
+// only the processing of chunks past the last is skipped.
 constexpr int kDirectAhead = 5;
 // LDS of a direct-mask workgroup: the accumulators and up to
 // kDirectMaskBytes of segment masks, so that two workgroups share a CU.
@@ -532,12 +551,10 @@ constexpr size_t kDirectLds = kRowBlock * sizeof(uint32_t) + kDirectMaskBytes;
 
 template <int WAVES, int NP>
 __global__ void __launch_bounds__(64 * WAVES, 2)
-k_label_direct(const uint32_t *__restrict__ block_tile, const uint64_t *__restrict__ tile_e0,
-               const uint32_t *__restrict__ tile_chunk, const uint32_t *__restrict__ tile_seg,
+k_label_direct(const uint32_t *__restrict__ tile_part, const DirectPart *__restrict__ parts,
                const SpChunk *__restrict__ chunks, const uint32_t *__restrict__ seg_word,
                const uint16_t *__restrict__ sp_row, const uint64_t *__restrict__ sp_val,
-               const uint64_t *__restrict__ Tm, uint32_t *__restrict__ P, const uint32_t *__restrict__ tile_slot,
-               const uint16_t *__restrict__ slot_row)
+               const uint64_t *__restrict__ Tm, uint64_t n_traj, uint32_t n_props, uint8_t *__restrict__ L)
 {
     static_assert(NP == 1 || NP == 2 || NP == 4, "direct masks: 1, 2 or 4 per word");
     constexpr int R = kDirectAhead + 1;
@@ -548,75 +565,84 @@ k_label_direct(const uint32_t *__restrict__ block_tile, const uint64_t *__restri
     typedef __attribute__((address_space(1))) const uint16_t gu16;
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(3))) const uint64_t lu64;
+    static_assert(sizeof(SpChunk) == 16, "a chunk record is four dwords");
+    static_assert(sizeof(DirectPart) == 32, "a part record is eight dwords");
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t tile = block_tile[blockIdx.x];
-    const uint32_t c0 = tile_chunk[tile], c1 = tile_chunk[tile + 1];
-    const uint32_t seg_first = tile_seg[2 * tile], n_seg = tile_seg[2 * tile + 1];
-    // chunks wave, wave + WAVES, ... of the tile
-    const uint32_t n = c1 - c0 > wave ? (c1 - c0 - wave + WAVES - 1) / WAVES : 0u;
-    // chunk k of this wavefront: record recs[4 k WAVES ..], entries from vals[64 k WAVES]
-    const gu32 *recs = (const gu32 *)(chunks + c0 + wave);
-    const gu64 *vals = (const gu64 *)(sp_val + tile_e0[tile] + 64ull * wave);
-    const gu16 *rows = (const gu16 *)(sp_row + tile_e0[tile] + 64ull * wave);
-    static_assert(sizeof(SpChunk) == 16, "a chunk record is four dwords");
+    const uint32_t p0 = tile_part[blockIdx.x], p1 = tile_part[blockIdx.x + 1];
+    for (uint32_t pi = p0; pi < p1; ++pi) {
+        const DirectPart part = parts[pi];
+        // chunks wave, wave + WAVES, ... of the part
+        const uint32_t nc = part.c1 - part.c0;
+        const uint32_t n = nc > wave ? (nc - wave + WAVES - 1) / WAVES : 0u;
+        const gu32 *recs = (const gu32 *)(chunks + part.c0 + wave);
+        const gu64 *vals = (const gu64 *)(sp_val + part.e0 + 64ull * wave);
+        const gu16 *rows = (const gu16 *)(sp_row + part.e0 + 64ull * wave);
 
-    struct Stage {
-        uint32_t rec;  // lanes 0-3: the chunk's record
-        uint64_t x;    // this lane's word value
-        uint16_t r;    // its local row
-    };
-    Stage st[R];
-    const uint32_t last = n ? n - 1 : 0u;
-    auto fetch = [&](Stage &q, uint32_t k) {
-        const uint32_t kk = min(k, last);
-        q.rec = recs[(uint64_t)kk * (4 * WAVES) + (lane & 3u)];
-        const uint64_t o = (uint64_t)kk * (64 * WAVES);
-        q.x = (vals + o)[lane];
-        q.r = (rows + o)[lane];
-    };
-    auto process = [&](const Stage &q) {
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 0);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 1);
-        const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 2);
-        const uint32_t nv = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 3);
-        const uint32_t seg = s0 + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const lu64 *m = (const lu64 *)(msk + seg * NP);
-        uint32_t a = 0;
+        struct Stage {
+            uint32_t rec;  // lanes 0-3: the chunk's record
+            uint64_t x;    // this lane's word value
+            uint16_t r;    // its local row
+        };
+        Stage st[R];
+        const uint32_t last = n ? n - 1 : 0u;
+        auto fetch = [&](Stage &q, uint32_t k) {
+            const uint32_t kk = min(k, last);
+            q.rec = recs[(uint64_t)kk * (4 * WAVES) + (lane & 3u)];
+            const uint64_t o = (uint64_t)kk * (64 * WAVES);
+            q.x = (vals + o)[lane];
+            q.r = (rows + o)[lane];
+        };
+        auto process = [&](const Stage &q) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 0);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 1);
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 2);
+            const uint32_t nv = (uint32_t)__builtin_amdgcn_readlane((int)q.rec, 3);
+            const uint32_t seg = s0 + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            const lu64 *m = (const lu64 *)(msk + seg * NP);
+            uint32_t a = 0;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) a |= (uint32_t)((q.x & m[p]) != 0ull) << p;
-        if (lane < nv && a) __hip_atomic_fetch_or(acc + q.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
+            for (int p = 0; p < NP; ++p) a |= (uint32_t)((q.x & m[p]) != 0ull) << p;
+            if (lane < nv && a) __hip_atomic_fetch_or(acc + q.r, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
 
-    // the first chunks' loads are issued before the accumulators are cleared
-    // and the masks copied (a wavefront without chunks loads nothing: its
-    // clamped indices would point past the tile)
-    if (n > 0) {
+        // the first chunks' loads are issued before the accumulators are
+        // cleared and the masks copied (a wavefront without chunks loads
+        // nothing: its clamped indices would point past the part)
+        if (n > 0) {
 #pragma unroll
-        for (int k = 0; k < kDirectAhead; ++k) fetch(st[k], k);
-    }
-    for (uint32_t i = threadIdx.x; i < kRowBlock / 4; i += 64 * WAVES)
-        reinterpret_cast<v4u32 *>(acc)[i] = v4u32{0u, 0u, 0u, 0u};
-    for (uint32_t i = threadIdx.x; i < n_seg; i += 64 * WAVES) {
-        const gu64 *src = (const gu64 *)(Tm + (uint64_t)seg_word[seg_first + i] * NP);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) msk[i * NP + p] = src[p];
-    }
-    __syncthreads();
-    for (uint32_t k0 = 0; k0 < n; k0 += R) {
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const uint32_t k = k0 + u;
-            fetch(st[(u + kDirectAhead) % R], k + kDirectAhead);
-            if (k < n) process(st[u]);
+            for (int k = 0; k < kDirectAhead; ++k) fetch(st[k], k);
         }
-    }
-    __syncthreads();
-    if (tile_slot) {
-        const uint32_t s0 = tile_slot[tile], s1 = tile_slot[tile + 1];
-        write_partials_compact<WAVES, uint32_t>(acc, P + s0, slot_row + s0, s1 - s0);
-    } else {
-        write_partials<WAVES, uint32_t>(acc, P + (uint64_t)tile * kRowBlock);
+        for (uint32_t i = threadIdx.x; i < kRowBlock / 4; i += 64 * WAVES)
+            reinterpret_cast<v4u32 *>(acc)[i] = v4u32{0u, 0u, 0u, 0u};
+        for (uint32_t i = threadIdx.x; i < part.n_seg; i += 64 * WAVES) {
+            const gu64 *src = (const gu64 *)(Tm + (uint64_t)seg_word[part.seg_first + i] * NP);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) msk[i * NP + p] = src[p];
+        }
+        __syncthreads();
+        for (uint32_t k0 = 0; k0 < n; k0 += R) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const uint32_t k = k0 + u;
+                fetch(st[(u + kDirectAhead) % R], k + kDirectAhead);
+                if (k < n) process(st[u]);
+            }
+        }
+        __syncthreads();
+        // the part's labels: a 1 for every set bit of a non-zero accumulator
+        const uint64_t t0 = (uint64_t)part.rb * kRowBlock;
+        for (uint32_t r = threadIdx.x; r < kRowBlock; r += 64 * WAVES) {
+            const uint32_t v = acc[r];
+            if (v && t0 + r < n_traj) {
+                __attribute__((address_space(1))) uint8_t *dst =
+                    (__attribute__((address_space(1))) uint8_t *)(L + (t0 + r) * n_props);
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    if ((v >> p) & 1u) dst[p] = 1;
+            }
+        }
+        __syncthreads();  // the accumulators and masks are reused by the next part
     }
 }
 
@@ -1293,41 +1319,62 @@ bool make_compact(const TilingHost &h, const std::vector<uint16_t> &row, const s
     return true;
 }
 
-void make_chunks(const TilingHost &h, const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg,
-                 ChunkHost *out)
+void make_direct(const std::vector<uint64_t> &seg_start, const std::vector<uint64_t> &rb_seg, uint32_t n_tiles,
+                 DirectHost *out)
 {
     const size_t n_rb = rb_seg.size() - 1;
-    const uint32_t n_tiles = (uint32_t)(h.tasks.size() / kTileWaves);
-    out->tile_e0.assign(n_tiles, 0);
-    out->tile_chunk.assign(n_tiles + 1, 0);
-    out->tile_seg.assign(2 * (size_t)n_tiles, 0);
     out->chunks.clear();
+    out->parts.clear();
+    // the chunks of every row block, and the first chunk of each block
+    std::vector<uint64_t> rb_chunk(n_rb + 1, 0);
     for (size_t rb = 0; rb < n_rb; ++rb) {
-        const uint64_t E1 = seg_start[rb_seg[rb + 1]];
-        uint64_t sg = rb_seg[rb];  // segment holding the chunk's first entry
-        for (uint32_t t = h.rb_tile[rb]; t < h.rb_tile[rb + 1]; ++t) {
-            const uint64_t lo = h.tasks[(size_t)t * kTileWaves].lo;
-            const uint64_t hi = t + 1 < h.rb_tile[rb + 1] ? h.tasks[(size_t)(t + 1) * kTileWaves].lo : E1;
-            out->tile_e0[t] = lo;
-            uint64_t first = sg, end = sg;
-            if (lo < hi) {
-                while (seg_start[sg + 1] <= lo) ++sg;
-                first = sg;
-                end = sg + 1;
-            }
-            for (uint64_t a = lo; a < hi; a += 64) {
-                const uint64_t b = std::min(a + 64, hi);
-                while (seg_start[sg + 1] <= a) ++sg;
-                SpChunk c{0ull, (uint32_t)(sg - first), (uint32_t)(b - a)};
-                uint64_t q = sg + 1;
-                for (; q < rb_seg[rb + 1] && seg_start[q] < b; ++q) c.starts |= 1ull << (seg_start[q] - a - 1);
-                end = std::max(end, q);
-                out->chunks.push_back(c);
-            }
-            out->tile_chunk[t + 1] = (uint32_t)out->chunks.size();
-            out->tile_seg[2 * t] = (uint32_t)first;
-            out->tile_seg[2 * t + 1] = (uint32_t)(end - first);
+        const uint64_t E0 = seg_start[rb_seg[rb]], E1 = seg_start[rb_seg[rb + 1]];
+        rb_chunk[rb + 1] = rb_chunk[rb] + (E1 - E0 + 63) / 64;
+    }
+    const uint64_t C = rb_chunk[n_rb];
+    n_tiles = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, C));
+    out->tile_part.assign(n_tiles + 1, 0);
+    // chunk records: seg0 is fixed once the parts are known (relative to the
+    // part's first segment), so first record each chunk's segment
+    std::vector<uint64_t> chunk_seg(C);
+    for (size_t rb = 0; rb < n_rb; ++rb) {
+        const uint64_t E0 = seg_start[rb_seg[rb]], E1 = seg_start[rb_seg[rb + 1]];
+        uint64_t sg = rb_seg[rb];
+        for (uint64_t a = E0, c = rb_chunk[rb]; a < E1; a += 64, ++c) {
+            const uint64_t b = std::min(a + 64, E1);
+            while (seg_start[sg + 1] <= a) ++sg;
+            chunk_seg[c] = sg;
+            SpChunk ch{0ull, 0u, (uint32_t)(b - a)};
+            for (uint64_t q = sg + 1; q < rb_seg[rb + 1] && seg_start[q] < b; ++q)
+                ch.starts |= 1ull << (seg_start[q] - a - 1);
+            out->chunks.push_back(ch);
         }
+    }
+    // tiles of equal chunk counts, cut into one part per row block
+    size_t rb = 0;
+    for (uint32_t t = 0; t < n_tiles; ++t) {
+        const uint64_t lo = C * t / n_tiles, hi = C * (t + 1) / n_tiles;
+        uint64_t c = lo;
+        while (c < hi) {
+            while (rb_chunk[rb + 1] <= c) ++rb;
+            const uint64_t end = std::min(hi, rb_chunk[rb + 1]);
+            DirectPart p{};
+            p.e0 = seg_start[rb_seg[rb]] + 64 * (c - rb_chunk[rb]);
+            p.c0 = (uint32_t)c;
+            p.c1 = (uint32_t)end;
+            p.rb = (uint32_t)rb;
+            p.seg_first = (uint32_t)chunk_seg[c];
+            // the part's last segment: that of its last entry
+            const uint64_t last_e = seg_start[rb_seg[rb]] + 64 * (end - 1 - rb_chunk[rb]) + out->chunks[end - 1].n_valid - 1;
+            const uint64_t last_s = std::upper_bound(seg_start.begin() + (ptrdiff_t)chunk_seg[end - 1],
+                                                     seg_start.begin() + (ptrdiff_t)rb_seg[rb + 1], last_e) -
+                                    seg_start.begin() - 1;
+            p.n_seg = (uint32_t)(last_s + 1 - chunk_seg[c]);
+            for (uint64_t j = c; j < end; ++j) out->chunks[j].seg0 = (uint32_t)(chunk_seg[j] - chunk_seg[c]);
+            out->parts.push_back(p);
+            c = end;
+        }
+        out->tile_part[t + 1] = (uint32_t)out->parts.size();
     }
 }
 
@@ -1346,12 +1393,11 @@ SparseLayout::~SparseLayout()
         (void)hipFree(t.slot_row);
         (void)hipFree(t.row_slot_off);
         (void)hipFree(t.row_slots);
-        (void)hipFree(t.tile_e0);
-        (void)hipFree(t.tile_chunk);
-        (void)hipFree(t.tile_seg);
-        (void)hipFree(t.chunks);
-        (void)hipFree(t.seg_word);
     }
+    (void)hipFree(direct.tile_part);
+    (void)hipFree(direct.parts);
+    (void)hipFree(direct.chunks);
+    (void)hipFree(direct.seg_word);
 }
 
 void free_sparse(SparseLayout *sp) { delete sp; }
@@ -1405,26 +1451,27 @@ static lbl_status upload_compact(const CompactHost &c, SpTiling *t, size_t *byte
     return LBL_OK;
 }
 
-static lbl_status upload_chunks(const ChunkHost &c, const std::vector<uint32_t> &seg_word, SpTiling *t,
+static lbl_status upload_direct(const DirectHost &c, const std::vector<uint32_t> &seg_word, DirectLayout *d,
                                 size_t *bytes)
 {
-    // segment ids are 32-bit: larger layouts keep the nibble kernels only
+    // 32-bit chunk and segment ids: larger layouts keep the nibble kernels only
     if (seg_word.size() >= (1ull << 32) || c.chunks.size() >= (1ull << 32)) return LBL_OK;
-    t->n_chunks = c.chunks.size();
-    t->max_tile_segs = 0;
-    for (size_t i = 1; i < c.tile_seg.size(); i += 2) t->max_tile_segs = std::max(t->max_tile_segs, c.tile_seg[i]);
+    d->n_tiles = (uint32_t)(c.tile_part.size() - 1);
+    d->n_chunks = c.chunks.size();
+    d->n_parts = (uint32_t)c.parts.size();
+    d->max_part_segs = 0;
+    for (const DirectPart &p : c.parts) d->max_part_segs = std::max(d->max_part_segs, p.n_seg);
     auto up = [](void **dst, const void *src, size_t n) -> hipError_t {
         hipError_t e = hipMalloc(dst, std::max<size_t>(n, 1));
         if (e == hipSuccess && n) e = hipMemcpy(*dst, src, n, hipMemcpyHostToDevice);
         return e;
     };
-    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->tile_e0), c.tile_e0.data(), c.tile_e0.size() * 8));
-    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->tile_chunk), c.tile_chunk.data(), c.tile_chunk.size() * 4));
-    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->tile_seg), c.tile_seg.data(), c.tile_seg.size() * 4));
-    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->chunks), c.chunks.data(), c.chunks.size() * sizeof(SpChunk)));
-    LBL_HIP_TRY(up(reinterpret_cast<void **>(&t->seg_word), seg_word.data(), seg_word.size() * 4));
-    *bytes += c.tile_e0.size() * 8 + (c.tile_chunk.size() + c.tile_seg.size() + seg_word.size()) * 4 +
-              c.chunks.size() * sizeof(SpChunk);
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&d->tile_part), c.tile_part.data(), c.tile_part.size() * 4));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&d->parts), c.parts.data(), c.parts.size() * sizeof(DirectPart)));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&d->chunks), c.chunks.data(), c.chunks.size() * sizeof(SpChunk)));
+    LBL_HIP_TRY(up(reinterpret_cast<void **>(&d->seg_word), seg_word.data(), seg_word.size() * 4));
+    *bytes += c.tile_part.size() * 4 + c.parts.size() * sizeof(DirectPart) + c.chunks.size() * sizeof(SpChunk) +
+              seg_word.size() * 4;
     return LBL_OK;
 }
 
@@ -1612,12 +1659,14 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
             st = upload_compact(c, &sp->tilings[i], &sp->round_bytes);
             if (st != LBL_OK) return st;
         }
-        if (i == kNarrowTiling) {
-            ChunkHost ch;
-            make_chunks(h, seg_start, rb_seg, &ch);
-            st = upload_chunks(ch, seg_word, &sp->tilings[i], &sp->round_bytes);
-            if (st != LBL_OK) return st;
-        }
+
+    }
+    {
+        // the direct-mask kernel's tiles: two workgroups per CU
+        DirectHost dh;
+        make_direct(seg_start, rb_seg, 2 * n_cu, &dh);
+        lbl_status st = upload_direct(dh, seg_word, &sp->direct, &sp->round_bytes);
+        if (st != LBL_OK) return st;
     }
     LBL_HIP_TRY(hipDeviceSynchronize());
     a->sp = sp.release();
@@ -1679,38 +1728,33 @@ lbl_status run_swm_t(const lbl_abs *a, const SpTiling &tl, size_t lds, const uin
     return LBL_OK;
 }
 
-// The three kernels of a frame of at most NP <= 4 propositions on the
-// narrow tiling tl: per-word proposition masks, the direct-mask label kernel,
-// the combine.  The masks take the place of the 32-bit nibble tables in the
-// workspace (NP x 8 B per word against 1 KiB), the partials the same place.
+// The two kernels of a frame of at most NP <= 4 propositions: per-word
+// proposition masks (and L zeroed), then the direct-mask label kernel, which
+// writes L.  The masks take the place of the nibble tables in the workspace.
 template <int NP>
-lbl_status run_swm_direct(const lbl_abs *a, const SpTiling &tl, const uint8_t *O, uint32_t n_props, void *ws,
-                          uint8_t *L, hipStream_t s, bool spans)
+lbl_status run_swm_direct(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *ws, uint8_t *L,
+                          hipStream_t s, bool spans)
 {
     const SparseLayout &sp = *a->sp;
+    const DirectLayout &d = sp.direct;
     uint64_t *Tm = static_cast<uint64_t *>(ws);
-    uint32_t *P = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(ws) +
-                                               up256((size_t)a->n_words * 256 * sizeof(uint32_t)));
     auto span_begin = [&](hipStream_t st) { return spans ? lbl::span_begin(st) : nullptr; };
     auto span_end = [&](void *b, hipStream_t st, int kind) {
         if (spans) lbl::span_end(b, st, kind);
     };
+    const uint64_t n_L = a->n_traj * n_props;
+    const uint64_t pack_blocks = std::max<uint64_t>(((uint64_t)sp.n_used * 64 + 255) / 256,
+                                                    std::min<uint64_t>((n_L + 4095) / 4096, 1024));
     void *spn = span_begin(s);
-    hipLaunchKernelGGL(k_pack_masks<NP>, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tm);
+    hipLaunchKernelGGL(k_pack_masks<NP>, dim3((unsigned)pack_blocks), dim3(256), 0, s, O, n_props, a->d_word_cell,
+                       a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tm, L, n_L);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);
-    hipLaunchKernelGGL((k_label_direct<kTileWaves, NP>), dim3(tl.n_tiles), dim3(64 * kTileWaves), kDirectLds, s,
-                       tl.block_tile, tl.tile_e0, tl.tile_chunk, tl.tile_seg, tl.chunks, tl.seg_word, sp.row, sp.val,
-                       Tm, P, tl.tile_slot, tl.slot_row);
+    hipLaunchKernelGGL((k_label_direct<kTileWaves, NP>), dim3(d.n_tiles), dim3(64 * kTileWaves), kDirectLds, s,
+                       d.tile_part, d.parts, d.chunks, d.seg_word, sp.row, sp.val, Tm, a->n_traj, n_props, L);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 1);
-    spn = span_begin(s);
-    hipLaunchKernelGGL(k_combine<uint32_t>, dim3(grid_cap(a->n_traj, 256, 16384)), dim3(256), 0, s, P, tl.rb_tile,
-                       tl.row_slot_off, tl.row_slots, a->n_traj, n_props, L);
-    LBL_HIP_TRY(hipGetLastError());
-    span_end(spn, s, 3);
     return LBL_OK;
 }
 
@@ -1721,19 +1765,18 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
 {
     LBL_REQUIRE(a->sp != nullptr, "the abstraction has no sparse layout");
     const SparseLayout &sp = *a->sp;
-    // frames of at most 32 propositions take the 32-bit mask kernels, those
-    // of at most 4 the direct-mask kernel
-    if (n_props <= 32 && (int)sp.tilings.size() > kNarrowTiling) {
-        const SpTiling &tl = sp.tilings[kNarrowTiling];
-        // the direct-mask kernel holds a tile's segment masks in LDS
-        const uint32_t np = n_props <= 1 ? 1 : n_props <= 2 ? 2 : 4;
-        if (n_props <= 4 && tl.chunks && (size_t)tl.max_tile_segs * np * sizeof(uint64_t) <= kDirectMaskBytes) {
-            if (n_props == 1) return run_swm_direct<1>(a, tl, O, n_props, ws, L, s, spans);
-            if (n_props == 2) return run_swm_direct<2>(a, tl, O, n_props, ws, L, s, spans);
-            return run_swm_direct<4>(a, tl, O, n_props, ws, L, s, spans);
-        }
-        return run_swm_t<uint32_t>(a, tl, kTileLds32, O, n_props, ws, L, s, spans);
+    // frames of at most 4 propositions take the direct-mask kernel (which
+    // holds a part's segment masks in LDS), those of at most 32 the 32-bit
+    // mask kernels
+    const DirectLayout &d = sp.direct;
+    const uint32_t np = n_props <= 1 ? 1 : n_props <= 2 ? 2 : 4;
+    if (n_props <= 4 && d.chunks && (size_t)d.max_part_segs * np * sizeof(uint64_t) <= kDirectMaskBytes) {
+        if (n_props == 1) return run_swm_direct<1>(a, O, n_props, ws, L, s, spans);
+        if (n_props == 2) return run_swm_direct<2>(a, O, n_props, ws, L, s, spans);
+        return run_swm_direct<4>(a, O, n_props, ws, L, s, spans);
     }
+    if (n_props <= 32 && (int)sp.tilings.size() > kNarrowTiling)
+        return run_swm_t<uint32_t>(a, sp.tilings[kNarrowTiling], kTileLds32, O, n_props, ws, L, s, spans);
     return run_swm_t<uint64_t>(a, sp.tilings[0], kTileLds, O, n_props, ws, L, s, spans);
 }
 

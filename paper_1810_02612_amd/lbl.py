@@ -62,7 +62,8 @@ class AbsInfo(ctypes.Structure):
                 ("sparse_entries", ctypes.c_uint64), ("sparse_bytes", ctypes.c_uint64),
                 ("sparse_frame_bytes", ctypes.c_uint64), ("sparse_tiles", ctypes.c_uint32),
                 ("sparse_row_block", ctypes.c_uint32), ("sparse_frame_bytes_narrow", ctypes.c_uint64),
-                ("sparse_tiles_narrow", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("sparse_tiles_narrow", ctypes.c_uint32), ("sparse_tiles_direct", ctypes.c_uint32),
+                ("sparse_frame_bytes_direct", ctypes.c_uint64)]
 
 
 class Job(ctypes.Structure):

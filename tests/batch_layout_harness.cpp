@@ -398,43 +398,48 @@ static void check_tiling(const std::vector<uint64_t> &start, const std::vector<u
         CHECK(next == E1);
     }
     for (uint64_t e = 0; e < nnz; ++e) CHECK(seen[e] == 1);
-    // chunks of the direct-mask kernel: walked as the kernel does, every entry
-    // is taken once, by a valid lane of a chunk of its own tile, and finds its
-    // own segment among the tile's
-    {
-        ChunkHost ch;
-        make_chunks(h, start, rb_seg, &ch);
-        CHECK(ch.tile_chunk.size() == n_tiles + 1 && ch.tile_e0.size() == n_tiles && ch.tile_chunk[0] == 0);
-        CHECK(ch.tile_seg.size() == 2 * n_tiles && ch.tile_chunk[n_tiles] == ch.chunks.size());
+    // the direct-mask split: walked as the kernel does, every entry is taken
+    // once, by a valid lane of a chunk of a part in the entry's own row block,
+    // and every lane (valid or not) reads a segment inside its part's set,
+    // the valid ones their own; tiles hold equal chunk counts (within one)
+    for (uint32_t want_tiles : {1u, 7u, 512u}) {
+        DirectHost dh;
+        make_direct(start, rb_seg, want_tiles, &dh);
+        const uint32_t nt = (uint32_t)dh.tile_part.size() - 1;
+        CHECK(nt >= 1 && nt <= want_tiles && dh.tile_part[0] == 0 && dh.tile_part[nt] == dh.parts.size());
         std::vector<uint8_t> got(nnz, 0);
-        for (size_t rb = 0; rb < n_rb; ++rb)
-            for (uint32_t t = h.rb_tile[rb]; t < h.rb_tile[rb + 1]; ++t) {
-                const uint64_t lo = h.tasks[(size_t)t * kTileWaves].lo;
-                const uint64_t hi = t + 1 < h.rb_tile[rb + 1] ? h.tasks[(size_t)(t + 1) * kTileWaves].lo
-                                                               : start[rb_seg[rb + 1]];
-                const uint32_t first = ch.tile_seg[2 * t], n_seg = ch.tile_seg[2 * t + 1];
-                CHECK(ch.tile_e0[t] == lo);
-                CHECK(ch.tile_chunk[t + 1] - ch.tile_chunk[t] == (hi - lo + 63) / 64);
-                CHECK((n_seg == 0) == (lo == hi));
-                CHECK(n_seg == 0 || (first >= rb_seg[rb] && first + n_seg <= rb_seg[rb + 1]));
-                for (uint32_t j = ch.tile_chunk[t]; j < ch.tile_chunk[t + 1]; ++j) {
-                    const SpChunk &c = ch.chunks[j];
-                    const uint64_t a = lo + 64ull * (j - ch.tile_chunk[t]);
-                    CHECK(c.n_valid >= 1 && c.n_valid <= 64 && a + c.n_valid <= hi);
-                    CHECK(c.n_valid == 64 || a + c.n_valid == hi);
+        uint64_t cmin = ~0ull, cmax = 0, next_chunk = 0;
+        for (uint32_t t = 0; t < nt; ++t) {
+            uint64_t c_t = 0;
+            for (uint32_t pi = dh.tile_part[t]; pi < dh.tile_part[t + 1]; ++pi) {
+                const DirectPart &p = dh.parts[pi];
+                CHECK(p.c0 == next_chunk && p.c1 > p.c0 && p.c1 <= dh.chunks.size() && p.rb < n_rb);
+                next_chunk = p.c1;
+                c_t += p.c1 - p.c0;
+                const uint64_t E1 = start[rb_seg[p.rb + 1]];
+                CHECK(p.seg_first >= rb_seg[p.rb] && p.seg_first + p.n_seg <= rb_seg[p.rb + 1] && p.n_seg >= 1);
+                for (uint32_t j = p.c0; j < p.c1; ++j) {
+                    const SpChunk &c = dh.chunks[j];
+                    const uint64_t a = p.e0 + 64ull * (j - p.c0);
+                    CHECK(c.n_valid >= 1 && c.n_valid <= 64 && a + c.n_valid <= E1);
+                    CHECK(c.n_valid == 64 || a + c.n_valid == E1);
                     CHECK(c.n_valid == 64 || (c.starts >> (c.n_valid - 1)) == 0);
                     for (uint32_t l = 0; l < 64; ++l) {
-                        // every lane, valid or not, reads a mask inside the tile's set
                         const uint32_t seg = c.seg0 + (uint32_t)__builtin_popcountll(c.starts & ((1ull << l) - 1));
-                        CHECK(seg < n_seg);
+                        CHECK(seg < p.n_seg);
                         if (l >= c.n_valid) continue;
                         const uint64_t e = a + l;
                         const uint64_t s = std::upper_bound(start.begin(), start.end(), e) - start.begin() - 1;
-                        CHECK(first + seg == s);
+                        CHECK(p.seg_first + seg == s);
                         ++got[e];
                     }
                 }
             }
+            cmin = std::min(cmin, c_t);
+            cmax = std::max(cmax, c_t);
+        }
+        CHECK(next_chunk == dh.chunks.size());
+        CHECK(nnz == 0 || cmax <= cmin + 1);
         for (uint64_t e = 0; e < nnz; ++e) CHECK(got[e] == 1);
     }
     // compact partial slots: random local rows for the entries; every (row,
