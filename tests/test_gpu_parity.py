@@ -302,6 +302,39 @@ def test_morton_cell_ids_give_the_row_major_labels(cfg, cfg1, cfg2):
         assert np.array_equal(Or.cpu().numpy(), Oz)
 
 
+
+def test_direct_masks_and_their_fallback():
+    """Frames of at most 4 propositions take the direct-mask kernels (per-word
+    masks, no combine) unless a tile part's segment masks would not fit the
+    kernel's LDS; then the 32-bit nibble kernels run.  1,966,080 rows of one
+    random cell each on a 1024 x 1024 grid (240 row blocks of ~6,400 segments
+    of about one entry) put about 3,000 segments in a part: under the
+    one-proposition budget (6,144), over the four-proposition one (1,536).
+    The kernels that ran are told apart by the profile counts (the nibble
+    path launches a combine); both must equal the oracle."""
+    n_side, n_traj = 1024, 240 * 8192
+    rng = np.random.default_rng(240)
+    row_ptr = np.arange(n_traj + 1, dtype=np.uint64)
+    col_idx = rng.integers(0, n_side * n_side, n_traj).astype(np.uint32)
+    say(f"direct fallback: sparse-only load of {n_traj} single-cell rows on {n_side}^2")
+    h = lbl.load_abstraction(n_side, n_side, row_ptr, col_idx, lbl.LOAD_SPARSE_ONLY)
+    try:
+        info = lbl.abstraction_info(h)
+        assert info["sparse_tiles_direct"] > 0 and info["sparse_frame_bytes_direct"] > 0
+        O = (rng.random((n_side * n_side, 4)) < 0.3).astype(np.uint8)
+        want = oracle.label_csr(row_ptr, col_idx, n_side * n_side, O, threads=THREADS)
+        for n_props, direct in ((1, True), (4, False)):
+            say(f"direct fallback: {n_props} propositions, direct expected {direct}")
+            lbl.profile_enable(True)
+            L = label(h, O[:, :n_props], n_traj, lbl.KERNEL_SPARSE)
+            prof = lbl.profile_read()
+            lbl.profile_enable(False)
+            assert prof["label_launches"] == 1
+            assert (prof["emit_launches"] == 0) == direct, prof
+            assert_same(L, want[:, :n_props], f"direct fallback, {n_props} propositions")
+    finally:
+        lbl.free_abstraction(h)
+
 def test_errors_on_device():
     rng = np.random.default_rng(1)
     a = random_csr(rng, 10, 8, 8, 0.2)

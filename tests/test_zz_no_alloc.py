@@ -89,6 +89,12 @@ def test_noalloc_equals_label_frame_large_then_small():
         same(a3, wb, "large again: noalloc vs oracle")
         a4, _ = both(hs, Os, small.n_traj, s2)
         same(a4, ws, "small again: noalloc vs oracle")
+        # two propositions: the direct-mask kernels, whose word masks take the
+        # array's front and which write L without a combine
+        say("noalloc: call 5, 200,000 x 512^2 x 2")
+        a5, b5 = both(hb, np.ascontiguousarray(Ob[:, :2]), big.n_traj, s2)
+        same(a5, b5, "two propositions: noalloc vs label_frame")
+        same(a5, wb[:, :2], "two propositions: noalloc vs oracle")
     finally:
         lbl.free_abstraction(hb)
         lbl.free_abstraction(hs)
