@@ -102,8 +102,10 @@ typedef struct {
 #define LBL_KERNEL_AUTO 0x00u   /* kernel and tile chosen by the autotuner cache */
 #define LBL_KERNEL_BITS 0x10u   /* bitpacked AND/OR wavefront kernel (dense bitpacked T) */
 #define LBL_KERNEL_SPARSE 0x80u /* sparse tiled T (non-zero words only), nibble
-                                   tables per word (needs the sparse layout,
-                                   built by default) */
+                                   tables per word, or for frames of at most
+                                   4 propositions per-word proposition masks
+                                   (needs the sparse layout, built by
+                                   default) */
 #define LBL_KERNEL_MFMA 0x20u   /* int8 MFMA kernel, T expanded from its bitpacked copy */
 #define LBL_KERNEL_MFMA_I8 0x40u /* int8 MFMA kernel reading the int8 copy of T
                                    (needs LBL_LOAD_KEEP_INT8) */

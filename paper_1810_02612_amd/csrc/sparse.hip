@@ -35,6 +35,13 @@
 //                  labels.
 //   k_combine      OR of a row's partials over the tiles of its row block ->
 //                  the caller's L bytes (0/1).
+// Frames of at most 4 propositions take two other kernels instead:
+//   k_pack_masks   O -> NP proposition masks per used word (bit b = cell b);
+//                  the grid also zeroes L.
+//   k_label_direct one workgroup per tile of equal chunk count: a label bit
+//                  is (word value AND mask) != 0, with the masks of the
+//                  tile's segments staged in LDS; the tile stores 1 into L's
+//                  bytes for the bits its rows' accumulators hold.
 // OR is idempotent and commutative, so neither the order of the LDS atomics
 // nor the split into tiles changes the result.  No global atomics are used.
 #include <algorithm>
