@@ -139,6 +139,7 @@ struct SparseLayout {
     uint64_t *val = nullptr;     // device [nnz] word value
     uint32_t n_used = 0;         // words held by some entry (their tables are packed per frame)
     uint32_t *used_words = nullptr;  // device [n_used] ascending, or null when every word is used
+    uint32_t *pack_first = nullptr;  // device [n_used] the first cell id of each packed word
     // tilings[0]: one frame (about one tile per CU, tiles of equal cost);
     // tilings[1 + i]: 2^i tiles per row block (batches); tilings[kNarrowTiling]:
     // one frame of at most 32 propositions (about two tiles per CU)

@@ -166,25 +166,30 @@ typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 
 // One wavefront per word, one lane per cell: the mask of the propositions
-// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].  With
-// row-major cell ids the word's first cell is read once per wavefront (a
-// scalar load) and lane b's cell lies dy rows and dx columns from it, x
-// taking the odd bits of b; with z-order ids (morton) lane b's cell is
-// w * 64 + b.  Wavefront i packs word words[i], or word i when words is null:
-// only words that some entry of the layout holds need tables.
+// cell (w, lane) meets, then the word's nibble tables Tg[w * 256 ..].
+// Wavefront i packs word words[i], or word i when words is null (only words
+// that some entry of the layout holds need tables), whose first cell is
+// first[i] (read once per wavefront, with no load before it): with row-major
+// cell ids lane b's cell lies dy rows and dx columns from it, x taking the
+// odd bits of b; with z-order ids (morton) it is first + b.
+__device__ __forceinline__ uint64_t word_lane_cell(const uint32_t *__restrict__ first, uint32_t i, uint32_t lane,
+                                                   uint32_t nx, uint32_t morton)
+{
+    const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
+    const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
+    return (uint64_t)first[i] + (morton ? (uint64_t)lane : (uint64_t)dy * nx + dx);
+}
+
 template <typename M>
 __global__ void __launch_bounds__(256)
-k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
+k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ first, uint32_t nx,
               uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, M *__restrict__ Tg)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n_items) return;  // whole wavefronts
     const uint32_t w = words ? words[i] : i;
-    const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
-    const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
-    const uint64_t cell = morton ? (uint64_t)w * 64 + lane
-                                 : (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
+    const uint64_t cell = word_lane_cell(first, i, lane, nx, morton);
     const uint64_t mask = byte_mask(O + cell * n_props, n_props);
     if constexpr (sizeof(M) == 8)
         write_tables(mask, Tg + (uint64_t)w * 256, lane);
@@ -194,13 +199,13 @@ k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *_
 
 
 // Frames of at most NP <= 4 propositions: one wavefront per word, lane b
-// holding cell b as in k_pack_tables; the word's NP proposition masks
+// holding cell b of packed word i as in k_pack_tables; the word's NP proposition masks
 // Tm[w * NP + p] (bit b set iff cell b meets proposition p; zero for
 // p >= n_props), lane p writing mask p.  The grid also zeroes the frame's
 // n_L label bytes at L, which the label kernel then sets where true.
 template <int NP>
 __global__ void __launch_bounds__(256)
-k_pack_masks(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ word_cell, uint32_t nx,
+k_pack_masks(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ first, uint32_t nx,
              uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, uint64_t *__restrict__ Tm,
              uint8_t *__restrict__ L, uint64_t n_L)
 {
@@ -220,10 +225,7 @@ k_pack_masks(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__
     const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n_items) return;  // whole wavefronts
     const uint32_t w = words ? words[i] : i;
-    const uint32_t dx = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
-    const uint32_t dy = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
-    const uint64_t cell = morton ? (uint64_t)w * 64 + lane
-                                 : (uint64_t)word_cell[(uint64_t)w * 64] + (uint64_t)dy * nx + dx;
+    const uint64_t cell = word_lane_cell(first, i, lane, nx, morton);
     const uint64_t mine = byte_mask(O + cell * n_props, n_props);
     uint64_t mp = 0;
 #pragma unroll
@@ -1390,6 +1392,7 @@ SparseLayout::~SparseLayout()
     (void)hipFree(row);
     (void)hipFree(val);
     (void)hipFree(used_words);
+    (void)hipFree(pack_first);
     for (SpTiling &t : tilings) {
         (void)hipFree(t.tasks);
         (void)hipFree(t.rounds);
@@ -1628,6 +1631,20 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
     for (uint32_t w = 0; w < W; ++w)
         if (used[w]) used_list.push_back(w);
     sp->n_used = (uint32_t)used_list.size();
+    // every word is packed when every word is used (or none: the tables are
+    // then unread)
+    if (sp->n_used == W || sp->n_used == 0) {
+        used_list.resize(W);
+        for (uint32_t w = 0; w < W; ++w) used_list[w] = w;
+    }
+    {
+        std::vector<uint32_t> first(used_list.size());
+        for (size_t i = 0; i < used_list.size(); ++i)
+            first[i] = a->order.morton ? used_list[i] * 64u : a->order.word_cell[(uint64_t)used_list[i] * 64];
+        LBL_HIP_TRY(hipMalloc(&sp->pack_first, std::max<size_t>(first.size(), 1) * sizeof(uint32_t)));
+        if (!first.empty())
+            LBL_HIP_TRY(hipMemcpy(sp->pack_first, first.data(), first.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
     if (sp->n_used < W && sp->n_used > 0) {
         LBL_HIP_TRY(hipMalloc(&sp->used_words, used_list.size() * sizeof(uint32_t)));
         LBL_HIP_TRY(hipMemcpy(sp->used_words, used_list.data(), used_list.size() * sizeof(uint32_t),
@@ -1719,7 +1736,7 @@ lbl_status run_swm_t(const lbl_abs *a, const SpTiling &tl, size_t lds, const uin
     };
     void *spn = span_begin(s);
     hipLaunchKernelGGL(k_pack_tables<M>, dim3((unsigned)(((uint64_t)sp.n_used * 64 + 255) / 256)), dim3(256), 0, s, O,
-                       n_props, a->d_word_cell, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
+                       n_props, sp.pack_first, a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tg);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
     spn = span_begin(s);
@@ -1753,7 +1770,7 @@ lbl_status run_swm_direct(const lbl_abs *a, const uint8_t *O, uint32_t n_props, 
     const uint64_t pack_blocks = std::max<uint64_t>(((uint64_t)sp.n_used * 64 + 255) / 256,
                                                     std::min<uint64_t>((n_L + 4095) / 4096, 1024));
     void *spn = span_begin(s);
-    hipLaunchKernelGGL(k_pack_masks<NP>, dim3((unsigned)pack_blocks), dim3(256), 0, s, O, n_props, a->d_word_cell,
+    hipLaunchKernelGGL(k_pack_masks<NP>, dim3((unsigned)pack_blocks), dim3(256), 0, s, O, n_props, sp.pack_first,
                        a->nx, (uint32_t)a->order.morton, sp.used_words, sp.n_used, Tm, L, n_L);
     LBL_HIP_TRY(hipGetLastError());
     span_end(spn, s, 0);
