@@ -303,6 +303,32 @@ def test_morton_cell_ids_give_the_row_major_labels(cfg, cfg1, cfg2):
 
 
 
+
+@pytest.mark.parametrize("n_props", [1, 2, 4, 8, 64])
+def test_empty_and_single_entry_abstractions(n_props):
+    """Degenerate layouts: no set cell at all (every label 0, every byte of L
+    still written), and one trajectory with one set cell (labels equal that
+    cell's row of O), with every kernel and the direct-mask, narrow and wide
+    mask widths."""
+    rng = np.random.default_rng(n_props)
+    nx = ny = 64
+    O = rng.integers(0, 2, (nx * ny, n_props)).astype(np.uint8)
+    O[1234] = 1  # the single entry's cell meets every proposition
+    cases = {
+        "empty": (np.zeros(301, np.uint64), np.zeros(0, np.uint32), 300),
+        "one cell": (np.array([0, 1], np.uint64), np.array([1234], np.uint32), 1),
+    }
+    for what, (row_ptr, col_idx, n_traj) in cases.items():
+        say(f"degenerate {what}, {n_props} propositions")
+        h = lbl.load_abstraction(nx, ny, row_ptr, col_idx, lbl.LOAD_KEEP_INT8)
+        try:
+            want = oracle.label_csr(row_ptr, col_idx, nx * ny, O)
+            assert want.sum() == (0 if what == "empty" else n_props)
+            for name, k in KERNELS.items():
+                assert_same(label(h, O, n_traj, k), want, f"{what}/{name}/{n_props}")
+        finally:
+            lbl.free_abstraction(h)
+
 def test_direct_masks_and_their_fallback():
     """Frames of at most 4 propositions take the direct-mask kernels (per-word
     masks, no combine) unless a tile part's segment masks would not fit the
