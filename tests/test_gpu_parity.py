@@ -201,6 +201,8 @@ def test_ragged_shapes(nx, ny, n_traj, n_props):
         want = expect(a, O)
         for name, k in KERNELS.items():
             assert_same(label(h, O, n_traj, k), want, f"ragged/{name}")
+        # host O and L (staged through device buffers), whichever mask width
+        assert_same(label(h, O, n_traj, lbl.KERNEL_SPARSE, host=True), want, "ragged/sparse/host")
     finally:
         lbl.free_abstraction(h)
 
