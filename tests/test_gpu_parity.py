@@ -331,6 +331,31 @@ def test_empty_and_single_entry_abstractions(n_props):
         finally:
             lbl.free_abstraction(h)
 
+
+@pytest.mark.parametrize("n_props", [1, 2, 3, 8, 64])
+def test_unaligned_L_and_bytes_around_it(n_props):
+    """L starting 3 bytes into a larger device buffer (and ending off a
+    16-byte boundary): every label byte equals the oracle's and no byte
+    outside L changes (the direct-mask path zeroes L before the tiles set
+    it, by whole 16-byte units inside L only)."""
+    rng = np.random.default_rng(300 + n_props)
+    a = random_csr(rng, 5003, 48, 40, 0.06)
+    O = (rng.random((48 * 40, n_props)) < 0.2).astype(np.uint8)
+    want = expect(a, O)
+    h = lbl.load_abstraction(48, 40, a.row_ptr, a.col_idx)
+    try:
+        n = a.n_traj * n_props
+        buf = torch.full((n + 64,), 0xA5, dtype=torch.uint8, device="cuda")
+        Lv = buf[3:3 + n]
+        say(f"unaligned L, {n_props} propositions")
+        lbl.label_frame(h, torch.from_numpy(O).cuda(), n_props, Lv, flags=lbl.KERNEL_SPARSE)
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        assert (got[:3] == 0xA5).all() and (got[3 + n:] == 0xA5).all()
+        assert_same(got[3:3 + n].reshape(a.n_traj, n_props), want, f"unaligned L, {n_props} propositions")
+    finally:
+        lbl.free_abstraction(h)
+
 def test_direct_masks_and_their_fallback():
     """Frames of at most 4 propositions take the direct-mask kernels (per-word
     masks, no combine) unless a tile part's segment masks would not fit the
