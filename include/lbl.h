@@ -217,14 +217,16 @@ lbl_status lbl_label_frame(lbl_abs_t a, const uint8_t *O, uint32_t n_props, uint
  * n_props bytes, written 0/1) are device memory owned by the caller, and the
  * call is asynchronous on hip_stream.
  *
- * The frame's intermediates (nibble tables and tile partials, or packed
- * masks) go to one static device array of 96 MiB that each GPU the library
- * runs on holds until the process ends; the call allocates nothing.  Every
- * call on one GPU uses that GPU's array, so calls that overlap on one GPU
- * (two streams, or two host threads) race: serialize them.  A call whose
- * intermediates do not fit (grids of more than about 2^20 cells: the tables
- * take 2 KiB per 64-cell word) fails with LBL_EINVAL and names the size it
- * needs; lbl_label_frame serves such frames.
+ * The frame's intermediates (nibble tables and tile partials, per-word
+ * proposition masks, or packed masks) go to one static device array of
+ * 96 MiB that each GPU the library runs on holds until the process ends;
+ * the call allocates nothing.  Every call on one GPU uses that GPU's array,
+ * so calls that overlap on one GPU (two streams, or two host threads) race:
+ * serialize them.  A call whose intermediates do not fit fails with
+ * LBL_EINVAL and names the size it needs; lbl_label_frame serves such
+ * frames.  The need depends on the frame: 2 KiB per 64-cell word of nibble
+ * tables for more than 32 propositions (grids above about 2^20 cells do not
+ * fit), 1 KiB for 5 to 32, and 8, 16 or 32 bytes for at most 4.
  *
  * Errors: LBL_EINVAL for a null handle or pointer, n_props outside [1, 64],
  * the current device not being the abstraction's, or intermediates larger

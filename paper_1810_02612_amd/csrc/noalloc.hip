@@ -63,7 +63,7 @@ lbl_status lbl_label_frame_noalloc(lbl_abs_t a, const uint8_t *O, uint32_t n_pro
     LBL_REQUIRE(dev == a->device, "the current device is not the abstraction's device");
     const bool sparse = a->sp != nullptr;
     LBL_REQUIRE(sparse || a->T_bits != nullptr, "the abstraction holds no layout of T");
-    const size_t need = sparse ? swm_workspace_bytes(a) : (size_t)a->n_words * 64 * sizeof(uint64_t);
+    const size_t need = sparse ? swm_frame_workspace_bytes(a, n_props) : (size_t)a->n_words * 64 * sizeof(uint64_t);
     LBL_REQUIRE(need <= kScratchBytes, "the frame needs " + std::to_string(need) +
                                            " bytes of scratch; lbl_label_frame_noalloc holds " +
                                            std::to_string(kScratchBytes) + " (use lbl_label_frame)");

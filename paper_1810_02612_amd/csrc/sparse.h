@@ -184,6 +184,9 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts);
 // t (nibble tables + per-tile partial labels); for one frame (the defaults),
 // the larger of the 64-bit and the 32-bit mask paths.
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups = 1, int t = 0);
+// Workspace bytes run_swm needs for one frame of n_props propositions (the
+// kernels that frame takes).
+size_t swm_frame_workspace_bytes(const lbl_abs *a, uint32_t n_props);
 
 // Pack O, label through the tiled layout, write L (device pointers).
 // spans: record profiling events around the kernels (when profiling is on).

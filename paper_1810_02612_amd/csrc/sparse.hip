@@ -1706,6 +1706,34 @@ lbl_status build_sparse(lbl_abs *a)
     return sparse_assemble(a, parts);
 }
 
+namespace {
+
+// Whether a frame of n_props propositions takes the direct-mask kernels
+// (the layout has their split and a part's segment masks fit their LDS);
+// *np is then the masks per word (1, 2 or 4).
+bool takes_direct(const SparseLayout &sp, uint32_t n_props, uint32_t *np)
+{
+    *np = n_props <= 1 ? 1 : n_props <= 2 ? 2 : 4;
+    return n_props <= 4 && sp.direct.chunks != nullptr &&
+           (size_t)sp.direct.max_part_segs * *np * sizeof(uint64_t) <= kDirectMaskBytes;
+}
+
+}  // namespace
+
+size_t swm_frame_workspace_bytes(const lbl_abs *a, uint32_t n_props)
+{
+    const SparseLayout &sp = *a->sp;
+    uint32_t np = 0;
+    if (takes_direct(sp, n_props, &np)) return up256((size_t)a->n_words * np * sizeof(uint64_t));
+    auto bytes = [&](int ti, size_t mask) {
+        const SpTiling &tl = sp.tilings[ti];
+        const size_t partials = tl.tile_slot ? (size_t)tl.n_slots : (size_t)tl.n_tiles * kRowBlock;
+        return up256((size_t)a->n_words * 256 * mask) + partials * mask;
+    };
+    if (n_props <= 32 && (int)sp.tilings.size() > kNarrowTiling) return bytes(kNarrowTiling, sizeof(uint32_t));
+    return bytes(0, sizeof(uint64_t));
+}
+
 size_t swm_workspace_bytes(const lbl_abs *a, uint32_t n_lane_groups, int t)
 {
     auto bytes = [&](int ti, size_t mask) {
@@ -1792,9 +1820,8 @@ lbl_status run_swm(const lbl_abs *a, const uint8_t *O, uint32_t n_props, void *w
     // frames of at most 4 propositions take the direct-mask kernel (which
     // holds a part's segment masks in LDS), those of at most 32 the 32-bit
     // mask kernels
-    const DirectLayout &d = sp.direct;
-    const uint32_t np = n_props <= 1 ? 1 : n_props <= 2 ? 2 : 4;
-    if (n_props <= 4 && d.chunks && (size_t)d.max_part_segs * np * sizeof(uint64_t) <= kDirectMaskBytes) {
+    uint32_t np = 0;
+    if (takes_direct(sp, n_props, &np)) {
         if (n_props == 1) return run_swm_direct<1>(a, O, n_props, ws, L, s, spans);
         if (n_props == 2) return run_swm_direct<2>(a, O, n_props, ws, L, s, spans);
         return run_swm_direct<4>(a, O, n_props, ws, L, s, spans);

@@ -125,21 +125,30 @@ def test_noalloc_bitpacked_abstraction_and_ragged_rows():
 
 
 def test_noalloc_rejects_what_does_not_fit_and_allocates_nothing():
-    # 2048^2 cells = 65,536 words: 128 MiB of nibble tables, more than the array
+    # 2048^2 cells = 65,536 words: a frame of 40 propositions needs 128 MiB of
+    # 64-bit nibble tables, more than the array; one of 4 needs 2 MiB of
+    # per-word masks (the direct-mask kernels) and fits
     n = 2048
     row_ptr = np.array([0, 3, 3, 5], np.uint64)
     col_idx = np.array([0, n * n - 1, 12345, 7, 4000000], np.uint32)
-    say("noalloc: 2048^2 grid, expect a size error")
+    say("noalloc: 2048^2 grid, expect a size error at 40 propositions")
     h = lbl.load_abstraction(n, n, row_ptr, col_idx)
     try:
-        Od = torch.zeros((n * n, 4), dtype=torch.uint8, device="cuda")
-        Ld = torch.full((3, 4), 9, dtype=torch.uint8, device="cuda")
+        Od = torch.zeros((n * n, 40), dtype=torch.uint8, device="cuda")
+        Ld = torch.full((3, 40), 9, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         with pytest.raises(lbl.LblError) as e:
-            lbl.label_frame_noalloc(h, Od, 4, Ld)
+            lbl.label_frame_noalloc(h, Od, 40, Ld)
         assert "scratch" in str(e.value)
         torch.cuda.synchronize()
         assert (Ld.cpu().numpy() == 9).all()
+        say("noalloc: 2048^2 grid, 4 propositions fit")
+        rng = np.random.default_rng(4)
+        O4 = (rng.random((n * n, 4)) < 0.5).astype(np.uint8)
+        L4 = torch.full((3, 4), 9, dtype=torch.uint8, device="cuda")
+        lbl.label_frame_noalloc(h, torch.from_numpy(O4).cuda(), 4, L4)
+        torch.cuda.synchronize()
+        same(L4.cpu().numpy(), oracle.label_csr(row_ptr, col_idx, n * n, O4), "2048^2, 4 propositions")
     finally:
         lbl.free_abstraction(h)
     # free device memory is unchanged by calls on a stream lbl_label_frame
