@@ -180,17 +180,65 @@ __device__ __forceinline__ uint64_t word_lane_cell(const uint32_t *__restrict__ 
     return (uint64_t)first[i] + (morton ? (uint64_t)lane : (uint64_t)dy * nx + dx);
 }
 
+// Lane b's mask of the propositions cell b of packed word i meets (cell b as
+// word_lane_cell places it).  When n_props is 16, 32 or 64 and O is 16-byte
+// aligned, the wavefront reads the word's frame bytes in 16-byte units taken
+// in memory order (each row of 8 cells, or with z-order ids the whole word,
+// is one contiguous run of O), so that a load instruction covers whole cache
+// lines instead of a 16-byte piece of 64 different cells; each unit's 16 bits
+// go to their cell's place in the wavefront's 512-byte stage, from which lane
+// b then reads cell b.  Otherwise every lane reads its own cell's bytes.
+__device__ __forceinline__ uint64_t word_cell_mask(const uint8_t *__restrict__ O, uint32_t n_props,
+                                                   const uint32_t *__restrict__ first, uint32_t i, uint32_t lane,
+                                                   uint32_t nx, uint32_t morton, uint64_t *stage)
+{
+    if (!((n_props == 16 || n_props == 32 || n_props == 64) && (reinterpret_cast<uintptr_t>(O) & 15u) == 0))
+        return byte_mask(O + word_lane_cell(first, i, lane, nx, morton) * n_props, n_props);
+    const uint32_t sh = n_props == 16 ? 0u : n_props == 32 ? 1u : 2u;  // log2 of a cell's units
+    const uint32_t last = (1u << sh) - 1u;                               // loads per lane - 1
+    const uint64_t c0 = first[i];
+    uint4 q[4];
+    uint32_t at[4];
+    // all loads first (the clamped repeats stay in bounds and are not used)
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t u = lane + 64u * min(j, last);   // unit of the word in memory order
+        const uint32_t k = u >> sh, part = u & last;    // its cell in memory order, its part
+        const uint32_t x = k & 7u, y = k >> 3;          // the cell's place in the word's 8 x 8 block
+        const uint64_t cell = c0 + (morton ? (uint64_t)k : (uint64_t)y * nx + x);
+        q[j] = *reinterpret_cast<const uint4 *>(O + cell * n_props + 16u * part);
+        const uint32_t b = morton ? k
+                                  : (y & 1u) | ((x & 1u) << 1) | ((y & 2u) << 1) | ((x & 2u) << 2) | ((y & 4u) << 2) |
+                                        ((x & 4u) << 3);
+        at[j] = 4u * b + part;  // 16-bit slot of the unit's bits in the stage
+    }
+    // LDS accesses of one wavefront complete in issue order: the zeroing
+    // precedes the unit stores, which precede the reads (the barriers only
+    // keep the compiler from moving accesses across them)
+    stage[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    uint16_t *s16 = reinterpret_cast<uint16_t *>(stage);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+        if (j <= last) s16[at[j]] = (uint16_t)nz_bytes16(q[j]);
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t m = stage[lane];
+    __builtin_amdgcn_wave_barrier();
+    return m;
+}
+
 template <typename M>
 __global__ void __launch_bounds__(256)
 k_pack_tables(const uint8_t *__restrict__ O, uint32_t n_props, const uint32_t *__restrict__ first, uint32_t nx,
               uint32_t morton, const uint32_t *__restrict__ words, uint32_t n_items, M *__restrict__ Tg)
 {
+    __shared__ uint64_t stage[4][64];
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t i = blockIdx.x * 4 + wave;
     if (i >= n_items) return;  // whole wavefronts
     const uint32_t w = words ? words[i] : i;
-    const uint64_t cell = word_lane_cell(first, i, lane, nx, morton);
-    const uint64_t mask = byte_mask(O + cell * n_props, n_props);
+    const uint64_t mask = word_cell_mask(O, n_props, first, i, lane, nx, morton, stage[wave]);
     if constexpr (sizeof(M) == 8)
         write_tables(mask, Tg + (uint64_t)w * 256, lane);
     else

@@ -18,22 +18,69 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
 // Four bits -> four bytes 0/1 (bit k to byte k).
 __device__ __forceinline__ uint32_t spread_nib(uint32_t x) { return (x * 0x00204081u) & 0x01010101u; }
 
-// Bit p set iff byte p of src[0 .. n) is non-zero, n <= 64; 16- or 4-byte
-// loads when n and the address allow.
+// Nonzero bytes of 16 bytes -> 16 bits (bit k for byte k).
+__device__ __forceinline__ uint32_t nz_bytes16(const uint4 &q)
+{
+    return nz_bytes(q.x) | (nz_bytes(q.y) << 4) | (nz_bytes(q.z) << 8) | (nz_bytes(q.w) << 12);
+}
+
+// Bit p set iff byte p of src[0 .. n) is non-zero, 1 <= n <= 64; 16-, 4- or
+// 2-byte loads when n and the address allow.  A group of four loads is
+// issued before the first of its results is used (a loop that used each load
+// before issuing the next would wait out the memory latency once per load):
+// indices past the last piece repeat the last load, which stays in bounds,
+// and their bits are dropped by a select rather than a branch, which the
+// compiler would turn into a load under a branch again.
 __device__ __forceinline__ uint64_t byte_mask(const uint8_t *src, uint32_t n)
 {
     uint64_t m = 0;
     const uintptr_t a = reinterpret_cast<uintptr_t>(src);
     if ((n & 15u) == 0 && (a & 15u) == 0) {
-        for (uint32_t p = 0; p < n; p += 16) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(src + p);
-            const uint64_t bits = nz_bytes(q.x) | (nz_bytes(q.y) << 4) | (nz_bytes(q.z) << 8) | (nz_bytes(q.w) << 12);
-            m |= bits << p;
+        const uint32_t last = n / 16 - 1;  // at most 3
+        uint4 q[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) q[k] = reinterpret_cast<const uint4 *>(src)[min(k, last)];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint64_t b = (uint64_t)nz_bytes16(q[k]) << (16 * k);
+            m |= k <= last ? b : 0ull;
         }
     } else if ((n & 3u) == 0 && (a & 3u) == 0) {
-        for (uint32_t p = 0; p < n; p += 4) m |= (uint64_t)nz_bytes(*reinterpret_cast<const uint32_t *>(src + p)) << p;
+        const uint32_t last = n / 4 - 1;  // at most 15
+        for (uint32_t k0 = 0; k0 <= last; k0 += 4) {
+            uint32_t d[4];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) d[k] = reinterpret_cast<const uint32_t *>(src)[min(k0 + k, last)];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) {
+                const uint64_t b = (uint64_t)nz_bytes(d[k]) << ((4 * (k0 + k)) & 63u);
+                m |= k0 + k <= last ? b : 0ull;
+            }
+        }
+    } else if ((n & 1u) == 0 && (a & 1u) == 0) {
+        const uint32_t last = n / 2 - 1;  // at most 31
+        for (uint32_t k0 = 0; k0 <= last; k0 += 4) {
+            uint32_t h[4];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) h[k] = reinterpret_cast<const uint16_t *>(src)[min(k0 + k, last)];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) {
+                const uint32_t two = ((h[k] & 0xFFu) != 0 ? 1u : 0u) | ((h[k] >> 8) != 0 ? 2u : 0u);
+                const uint64_t b = (uint64_t)two << ((2 * (k0 + k)) & 63u);
+                m |= k0 + k <= last ? b : 0ull;
+            }
+        }
     } else {
-        for (uint32_t p = 0; p < n; ++p) m |= (uint64_t)(src[p] != 0) << p;
+        for (uint32_t p0 = 0; p0 < n; p0 += 4) {
+            uint32_t c[4];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) c[j] = src[min(p0 + j, n - 1)];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint64_t b = (uint64_t)(c[j] != 0 ? 1u : 0u) << ((p0 + j) & 63u);
+                m |= p0 + j < n ? b : 0ull;
+            }
+        }
     }
     return m;
 }

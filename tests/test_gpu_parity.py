@@ -356,6 +356,36 @@ def test_unaligned_L_and_bytes_around_it(n_props):
     finally:
         lbl.free_abstraction(h)
 
+@pytest.mark.parametrize("n_props", [6, 12, 20, 34, 48, 60, 62, 64])
+@pytest.mark.parametrize("o_off", [0, 1, 2, 4])
+def test_frame_bytes_at_every_load_width(n_props, o_off):
+    """O starting o_off bytes into a larger device buffer, for proposition
+    counts whose rows the table kernels read in 16-byte units taken in
+    memory order (64), in 16-, 4- or 2-byte pieces per cell (48, 60 and 12
+    and 20, 6 and 34 and 62: more than one group of four loads for 20, 34, 60
+    and 62) or, once O is moved off those alignments, byte by byte: every
+    label equals the oracle's."""
+    rng = np.random.default_rng(500 + 7 * n_props + o_off)
+    nx, ny = 48, 40
+    a = random_csr(rng, 9000, nx, ny, 0.04)
+    O = rng.integers(0, 256, (nx * ny, n_props)).astype(np.uint8)
+    O[rng.random(O.shape) < 0.85] = 0
+    want = expect(a, O)
+    h = lbl.load_abstraction(nx, ny, a.row_ptr, a.col_idx)
+    try:
+        n = O.size
+        buf = torch.zeros((n + 16,), dtype=torch.uint8, device="cuda")
+        buf[o_off:o_off + n] = torch.from_numpy(O.reshape(-1)).cuda()
+        Ov = buf[o_off:o_off + n]
+        L = torch.full((a.n_traj, n_props), 9, dtype=torch.uint8, device="cuda")
+        say(f"O at offset {o_off}, {n_props} propositions")
+        lbl.label_frame(h, Ov, n_props, L, flags=lbl.KERNEL_SPARSE)
+        torch.cuda.synchronize()
+        assert_same(L.cpu().numpy(), want, f"O offset {o_off}, {n_props} propositions")
+    finally:
+        lbl.free_abstraction(h)
+
+
 def test_direct_masks_and_their_fallback():
     """Frames of at most 4 propositions take the direct-mask kernels (per-word
     masks, no combine) unless a tile part's segment masks would not fit the
