@@ -329,6 +329,18 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p)
     return (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) const uint8_t *)p);
 }
 
+// A raw buffer resource over device memory from p, its base made
+// wavefront-uniform (buffer loads take the resource in scalar registers):
+// no stride and the largest record count, so that no offset below 4 GiB is
+// treated as out of range (gfx9 resource word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(u), 0, -1, 0x00020000);
+}
+
 // Dwords of one word's nibble tables a lane holds while copying them:
 // 4 entries of M, 32 bytes (64-bit masks) or 16 (32-bit).
 template <typename M>
@@ -375,15 +387,12 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
     M *tab = acc + kRowBlock + wave * (kRing * kTabWords);  // this wavefront's two tables
     // Every array read here is device memory.  The batch path takes these
     // pointers from its descriptors in memory, where the compiler cannot see
-    // their address space: without the casts it would issue flat loads,
-    // which count on the LDS wait counter too, so that every wait for the
-    // LDS would also wait for them.  The task's fields are moved to scalar
-    // registers for the same reason (loads through such pointers land in
-    // vector registers).
+    // their address space: without the casts (or the buffer resources below)
+    // it would issue flat loads, which count on the LDS wait counter too, so
+    // that every wait for the LDS would also wait for them.  The task's
+    // fields are moved to scalar registers for the same reason (loads
+    // through such pointers land in vector registers).
     typedef __attribute__((address_space(1))) const uint32_t gu32;
-    typedef __attribute__((address_space(1))) const uint16_t gu16;
-    typedef __attribute__((address_space(1))) const uint64_t gu64;
-    typedef __attribute__((address_space(1))) const v4u32 gu128;
     constexpr uint32_t kTbN = kTbDwords<M> / 4;  // 16-byte loads of table data per lane
     const gu32 *task = (const gu32 *)(wg_tasks + wave);
     const uint64_t tk_lo = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)task[0]) |
@@ -392,13 +401,11 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
     const uint32_t round0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)task[3]);
     static_assert(sizeof(SpTask) == 16, "task layout: lo, n_rounds, round0");
     {
-        const gu32 *rr = (const gu32 *)(rounds + round0);
-
         struct Stage {
             uint32_t rec;      // lanes 0-3: the record of the stage's next round
             uint32_t meta;
             uint64_t x;        // this lane's word value
-            uint16_t r;        // its local row
+            uint32_t r;        // its local row (zero-extended when loaded)
             v4u32 tb[kTbN];    // this lane's 32 (or 16) bytes of the table the round builds
         };
         // kStages rounds are in flight: round i is fetched (its entries and
@@ -410,13 +417,19 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
         // unconditional and in bounds (the entry arrays carry 64 entries of
         // padding past the last one, and the record index is clamped), since
         // branches around loads would make the compiler wait for all of them;
-        // validity is applied when the round is processed.  Each load takes a
-        // wavefront-uniform base and a per-lane offset, so that no per-lane
-        // 64-bit address arithmetic is needed.
-        auto load_rec = [&](uint32_t i) { return rr[(uint64_t)min(i, n - 1) * 4 + (lane & 3u)]; };
+        // validity is applied when the round is processed.
+        // The loads go through raw buffer resources built in scalar registers
+        // (a uniform base, a per-lane offset fixed for the walk, and the
+        // round's uniform offset added by the load itself): no per-lane
+        // address arithmetic in the loop.
+        const __amdgpu_buffer_rsrc_t r_rec = uniform_rsrc(rounds + round0);
+        const __amdgpu_buffer_rsrc_t r_val = uniform_rsrc(sp_val + tk_lo);
+        const __amdgpu_buffer_rsrc_t r_row = uniform_rsrc(sp_row + tk_lo);
+        const uint32_t o_rec = (lane & 3u) * 4u, o_val = lane * 8u, o_row = lane * 2u, o_tab = lane * kTbN * 16u;
+        auto load_rec = [&](uint32_t i) {
+            return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r_rec, (int)o_rec, (int)(min(i, n - 1) * 16u), 0);
+        };
         static_assert(sizeof(SpRound) == 16, "a round record is four dwords");
-        const gu64 *val_t = (const gu64 *)(sp_val + tk_lo);
-        const gu16 *row_t = (const gu16 *)(sp_row + tk_lo);
         auto fetch = [&](Stage &st, uint32_t i) {
             // the fields are read before the register is reloaded, so that the
             // reload can take the same register (no copy waiting for it)
@@ -424,16 +437,17 @@ __device__ __forceinline__ void tile_accumulate(const SpTask *__restrict__ wg_ta
             const uint32_t tword = (uint32_t)__builtin_amdgcn_readlane((int)st.rec, 1);
             st.meta = (uint32_t)__builtin_amdgcn_readlane((int)st.rec, 3);
             st.rec = load_rec(i + kStages);
-            st.x = (val_t + e_off)[lane];
-            st.r = (row_t + e_off)[lane];
+            st.x = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r_val, (int)o_val, (int)(e_off * 8u), 0));
+            st.r = __builtin_amdgcn_raw_buffer_load_b16(r_row, (int)o_row, (int)(e_off * 2u), 0);
             // a round that builds no table loads one line for the whole
             // wavefront (still unconditionally): the 2 KiB of its last table
             // would mostly come from L2, the 16 wavefronts' last tables
             // filling the CU's L1
-            const gu128 *src = (const gu128 *)(Tg + (uint64_t)tword * tg_stride);
-            const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? kTbN * lane : 0u;
+            const __amdgpu_buffer_rsrc_t r_tab = uniform_rsrc(Tg + (uint64_t)tword * tg_stride);
+            const uint32_t tl = (st.meta & (kMetaBuild0 | kMetaBuild1)) ? o_tab : 0u;
 #pragma unroll
-            for (uint32_t k = 0; k < kTbN; ++k) st.tb[k] = src[tl + k];
+            for (uint32_t k = 0; k < kTbN; ++k)
+                st.tb[k] = __builtin_amdgcn_raw_buffer_load_b128(r_tab, (int)tl, (int)(16u * k), 0);
         };
 
         // the two slot addresses live in vector registers for the whole walk
