@@ -122,6 +122,34 @@ def test_tuned_batch_still_matches(abstractions):
     check_jobs(jobs, wants, "tuned")
 
 
+def test_batch_with_frames_and_labels_off_alignment(abstractions):
+    """Every job's O and L start 1, 2 or 3 bytes into larger device buffers
+    (the pack stages a job's bytes from a dword boundary, the combine writes
+    the ends of each L block byte by byte): labels equal the oracle's and no
+    byte around an L changes."""
+    jobs, wants, bufs = [], [], []
+    for i, x in enumerate(abstractions[:4]):
+        for k in range(3):
+            O = frames_for(x, i, 200 + k)
+            n_props = O.shape[1]
+            off = 1 + (i + k) % 3
+            ob = torch.zeros((O.size + 8,), dtype=torch.uint8, device="cuda")
+            ob[off:off + O.size] = torch.from_numpy(O.reshape(-1)).cuda()
+            n_l = x.a.n_traj * n_props
+            lb = torch.full((n_l + 8,), 0xA5, dtype=torch.uint8, device="cuda")
+            jobs.append((x.h, ob[off:off + O.size], n_props, lb[off:off + n_l]))
+            wants.append(x.expect(O))
+            bufs.append((lb, off, n_l, n_props, x.a.n_traj))
+    say(f"batch of {len(jobs)} jobs with O and L at byte offsets 1-3")
+    lbl.label_batch(jobs)
+    torch.cuda.synchronize()
+    for j, ((lb, off, n_l, n_props, n_traj), want) in enumerate(zip(bufs, wants)):
+        got = lb.cpu().numpy()
+        assert (got[:off] == 0xA5).all() and (got[off + n_l:] == 0xA5).all(), f"job {j}: bytes around L changed"
+        if not np.array_equal(got[off:off + n_l].reshape(n_traj, n_props), want):
+            raise AssertionError(f"job {j} (offset {off}, {n_props} propositions) differs from the oracle")
+
+
 def test_batch_equals_single_frames(abstractions):
     jobs, wants = make_jobs(abstractions[:2], per_abs=2, seed=3)
     singles = []
