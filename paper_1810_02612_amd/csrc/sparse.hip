@@ -1738,6 +1738,12 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
                                             : std::vector<uint32_t>(sp->n_rb, 1u << (i - 1));
         TilingHost h;
         make_tiling(seg_start, seg_word, rb_seg, k, &h);
+        // the tile kernels address a task's entries (8 bytes each) and round
+        // records with 32-bit byte offsets
+        for (const SpTask &t : h.tasks)
+            LBL_REQUIRE((uint64_t)t.n_rounds * sizeof(SpRound) < (1ull << 32) &&
+                            (t.n_rounds == 0 || (uint64_t)h.rounds[t.round0 + t.n_rounds - 1].e_off + 64 < (1ull << 29)),
+                        "a tile task spans more entries than the tile kernels address");
         lbl_status st = upload_tiling(h, &sp->tilings[i], &sp->round_bytes);
         if (st != LBL_OK) return st;
         CompactHost c;
