@@ -17,8 +17,11 @@ constexpr uint32_t kTileWaves = 16;
 // of a round may load its entry without a bounds check.
 constexpr uint64_t kEntryPad = 64;
 // Rounds a wavefront has in flight (records, entries and table data loaded
-// ahead of the round being processed).
-constexpr int kStages = 3;
+// ahead of the round being processed).  Two: the entries and table data of
+// the next round load while a round is processed, its record one round
+// earlier.  Measured on the 200k x 512^2 frames (64 and 32 propositions),
+// one is 35% slower and three and four 3% and 6% slower than two.
+constexpr int kStages = 2;
 // Nibble tables a wavefront holds at once (a round touches at most two
 // segments).
 constexpr uint32_t kRing = 2;

@@ -29,7 +29,7 @@
 //                  active lane ORs the 16 entries selected by the nibbles of
 //                  its word value (the labels of that (row, word) pair for up
 //                  to 64 propositions) into the tile's per-row accumulators
-//                  with an LDS atomic.  Three rounds are in flight per
+//                  with an LDS atomic.  Two rounds are in flight per
 //                  wavefront (loads issued ahead of the round processed).
 //                  The accumulators are written once per tile as its partial
 //                  labels.
