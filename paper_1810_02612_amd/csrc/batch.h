@@ -51,7 +51,16 @@ struct GroupDesc {
     const uint16_t *sp_row;
     const uint64_t *sp_val;
     uint64_t max_entry;
-    uint64_t *P;                 // [G64][n_tiles][kRowBlock] (null when fused)
+    uint64_t *P;                 // [G64][n_slots] compact, else [G64][n_tiles][kRowBlock] (null when fused)
+    // compact partials (the tiling's slot lists; null: full partials): tile
+    // i writes slots tile_slot[i] .. tile_slot[i + 1] (local rows
+    // slot_row[..]); row t's slots are row_slots[row_slot_off[t] ..
+    // row_slot_off[t + 1])
+    const uint32_t *tile_slot;
+    const uint16_t *slot_row;
+    const uint32_t *row_slot_off;
+    const uint32_t *row_slots;
+    uint64_t n_slots;
     uint32_t n_tiles;
     uint32_t n_rb;
     uint32_t fused;              // one tile per row block: tiles write the label bytes

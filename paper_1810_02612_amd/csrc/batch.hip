@@ -318,8 +318,18 @@ void plan_finalize(BatchPlan &p, const BatchTile &tile)
             // one tile per row block: a tile's accumulators are its rows'
             // final labels, so it writes the label bytes and needs no partials
             d.fused = tl.n_tiles == d.n_rb ? 1u : 0u;
+            // partials of only the rows each tile touches, when the tiling
+            // has its slot lists
+            const bool compact = !d.fused && tl.tile_slot != nullptr;
+            d.tile_slot = compact ? tl.tile_slot : nullptr;
+            d.slot_row = compact ? tl.slot_row : nullptr;
+            d.row_slot_off = compact ? tl.row_slot_off : nullptr;
+            d.row_slots = compact ? tl.row_slots : nullptr;
+            d.n_slots = compact ? tl.n_slots : 0;
             p.p_off.push_back(p.p_bytes);
-            if (!d.fused) p.p_bytes += up256((size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t));
+            if (!d.fused)
+                p.p_bytes += up256((size_t)d.G64 * (compact ? tl.n_slots : (size_t)d.n_tiles * kRowBlock) *
+                                   sizeof(uint64_t));
         }
         // pack items: each pass's words in runs of up to 8, at least about
         // 128 items per CU (a run's descriptors are read once for its words)

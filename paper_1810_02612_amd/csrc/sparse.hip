@@ -562,9 +562,13 @@ template <int WAVES, typename M>
 __device__ __forceinline__ void write_partials_compact(const void *lds, M *__restrict__ Pt,
                                                        const uint16_t *__restrict__ slot_row, uint32_t n_slot)
 {
+    // device memory (the batch's pointers come from its descriptors)
+    typedef __attribute__((address_space(1))) M gm;
+    typedef __attribute__((address_space(1))) const uint16_t gu16;
     const M *acc = static_cast<const M *>(lds);
-    for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES)
-        __builtin_nontemporal_store(acc[slot_row[k]], Pt + k);
+    gm *dst = (gm *)Pt;
+    const gu16 *rows = (const gu16 *)slot_row;
+    for (uint32_t k = threadIdx.x; k < n_slot; k += 64 * WAVES) __builtin_nontemporal_store(acc[rows[k]], dst + k);
 }
 
 // One workgroup per tile of a single frame: workgroup b runs tile
@@ -724,12 +728,17 @@ template <typename M>
 __device__ __forceinline__ uint64_t row_slots_or(const M *__restrict__ P, const uint32_t *__restrict__ off,
                                                  const uint32_t *__restrict__ slots, uint64_t t)
 {
-    const uint32_t k0 = off[t], k1 = off[t + 1];
+    // device memory (the batch's pointers come from its descriptors)
+    typedef __attribute__((address_space(1))) const M gm;
+    typedef __attribute__((address_space(1))) const uint32_t gu32;
+    const gm *Pg = (const gm *)P;
+    const gu32 *og = (const gu32 *)off, *sg = (const gu32 *)slots;
+    const uint32_t k0 = og[t], k1 = og[t + 1];
     uint64_t bits = 0;
     for (uint32_t kb = k0; kb < k1; kb += 4) {
         M v[4];
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) v[j] = P[slots[min(kb + j, k1 - 1)]];
+        for (uint32_t j = 0; j < 4; ++j) v[j] = Pg[sg[min(kb + j, k1 - 1)]];
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j) bits |= v[j];
     }
@@ -838,17 +847,24 @@ __device__ __forceinline__ void emit_tile(uint64_t *lds, const GroupDesc &g, uin
 // One tile item of a batch: pass it.group, tile it.tile, lane group it.gi.
 // The pass's nibble tables are [w][G64][256].  Passes on a tiling with one
 // tile per row block (fused) write the label bytes themselves; the others
-// write partials [G64][n_tiles][kRowBlock] for k_combine_batch.
+// write partials for k_combine_batch: compact ([G64][n_slots], the rows each
+// tile touches) when the tiling has slot lists, else [G64][n_tiles][kRowBlock].
 template <int WAVES>
 __device__ __forceinline__ void batch_tile(const GroupDesc *__restrict__ groups, const TileItem &it, uint64_t *lds)
 {
     const GroupDesc &g = groups[it.group];
     tile_accumulate<WAVES, uint64_t>(g.sp_tasks + (uint64_t)it.tile * WAVES, g.sp_rounds, g.sp_row, g.sp_val,
                                      g.Ow + (uint64_t)it.gi * 256, (uint64_t)g.G64 * 256, lds);
-    if (g.fused)
+    if (g.fused) {
         emit_tile<WAVES>(lds, g, it.gi, it.tile);
-    else
+    } else if (g.tile_slot) {
+        typedef __attribute__((address_space(1))) const uint32_t gu32;
+        const uint32_t s0 = ((const gu32 *)g.tile_slot)[it.tile], s1 = ((const gu32 *)g.tile_slot)[it.tile + 1];
+        write_partials_compact<WAVES, uint64_t>(lds, g.P + (uint64_t)it.gi * g.n_slots + s0, g.slot_row + s0,
+                                                s1 - s0);
+    } else {
         write_partials<WAVES, uint64_t>(lds, g.P + ((uint64_t)it.gi * g.n_tiles + it.tile) * kRowBlock);
+    }
 }
 
 // One workgroup per tile item: workgroup b runs items[launch[b]].
@@ -1052,12 +1068,15 @@ k_combine_batch(const GroupDesc *__restrict__ groups, const CombineItem *__restr
     const uint32_t lane = threadIdx.x;
     const CombineItem it = items[blockIdx.x];
     const GroupDesc &g = groups[it.group];
-    const uint64_t *Pg = g.P + (uint64_t)it.gi * g.n_tiles * kRowBlock;
+    const bool compact = g.tile_slot != nullptr;
+    const uint64_t *Pg = g.P + (uint64_t)it.gi * (compact ? g.n_slots : (uint64_t)g.n_tiles * kRowBlock);
     const uint32_t s0 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[it.gi]);
     const uint32_t s1 = __builtin_amdgcn_readfirstlane((int)g.lg_seg[it.gi + 1]);
     for (uint64_t t0 = it.row0; t0 < it.row1; t0 += 64) {
         const uint64_t t = t0 + lane;
-        const uint64_t bits = t < it.row1 ? row_partials(Pg, g.sp_rb_tile, t) : 0ull;
+        uint64_t bits = 0;
+        if (t < it.row1)
+            bits = compact ? row_slots_or(Pg, g.row_slot_off, g.row_slots, t) : row_partials(Pg, g.sp_rb_tile, t);
         const uint32_t n = (uint32_t)min<uint64_t>(64, it.row1 - t0);
         for (uint32_t sgi = s0; sgi < s1; ++sgi) {
             const SegDesc d = uniform_seg(g.segs, sgi);
@@ -1747,7 +1766,7 @@ lbl_status sparse_assemble(lbl_abs *a, std::vector<SparsePart> &parts)
         lbl_status st = upload_tiling(h, &sp->tilings[i], &sp->round_bytes);
         if (st != LBL_OK) return st;
         CompactHost c;
-        if (one_frame && make_compact(h, rows_host, seg_start, rb_seg, a->n_traj, &c)) {
+        if (make_compact(h, rows_host, seg_start, rb_seg, a->n_traj, &c)) {
             st = upload_compact(c, &sp->tilings[i], &sp->round_bytes);
             if (st != LBL_OK) return st;
         }

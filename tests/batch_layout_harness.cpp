@@ -140,7 +140,11 @@ static void check_case(std::vector<lbl_abs> &abss, const std::vector<JobRef> &jo
             for (uint32_t rb = 0; rb < d.n_rb; ++rb) CHECK(tl.rb_tile_host[rb] == rb);
             continue;
         }
-        const size_t pb = (size_t)d.G64 * d.n_tiles * kRowBlock * sizeof(uint64_t);
+        // compact partials ([G64][n_slots]) when the tiling has slot lists
+        CHECK(d.tile_slot == tl.tile_slot && d.slot_row == tl.slot_row && d.row_slot_off == tl.row_slot_off &&
+              d.row_slots == tl.row_slots && d.n_slots == (tl.tile_slot ? tl.n_slots : 0));
+        const size_t pb =
+            (size_t)d.G64 * (d.tile_slot ? (size_t)d.n_slots : (size_t)d.n_tiles * kRowBlock) * sizeof(uint64_t);
         CHECK(inside(d.P, pb));
         p_ranges.push_back({reinterpret_cast<const uint8_t *>(d.P), reinterpret_cast<const uint8_t *>(d.P) + pb});
     }
@@ -303,6 +307,15 @@ static SparseLayout *fake_layout(uint64_t rows, uint64_t base)
             t.rb_tile_host[rb + 1] = t.rb_tile_host[rb] + k;
         }
         CHECK(t.rb_tile_host[sp->n_rb] == t.n_tiles);
+        // slot lists (compact partials) on the odd tilings, fewer slots than
+        // a full [n_tiles][kRowBlock] partial set
+        if (i & 1) {
+            t.n_slots = (uint64_t)t.n_tiles * kRowBlock / 3 + 7;
+            t.tile_slot = reinterpret_cast<uint32_t *>(base + 0x50000000ull + 0x1000000ull * i);
+            t.slot_row = reinterpret_cast<uint16_t *>(base + 0x60000000ull + 0x1000000ull * i);
+            t.row_slot_off = reinterpret_cast<uint32_t *>(base + 0x70000000ull + 0x1000000ull * i);
+            t.row_slots = reinterpret_cast<uint32_t *>(base + 0x80000000ull + 0x1000000ull * i);
+        }
     }
     return sp;
 }
