@@ -9,7 +9,9 @@
 // fit the arena: admission by memory) and launches it with the same
 // persistent kernel as lbl_label_batch, while earlier batches are still
 // running on the other slots.  Requests that arrive meanwhile join the next
-// batch.  Latency is completion minus submission on the host's monotonic
+// batch.  While batches are in flight the worker polls their completion
+// events every few microseconds (it sleeps on a condition variable only when
+// idle).  Latency is completion minus submission on the host's monotonic
 // clock.  A frame's columns never share lanes with another frame's, so its
 // labels do not depend on its batch-mates.
 #include <algorithm>
@@ -222,8 +224,15 @@ void worker_main(lbl_server *S)
             for (Slot &sl : S->slots) busy = busy || sl.busy;
             if (!busy) break;
         }
-        if (any_busy)
-            S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        if (any_busy) {
+            // batches are in flight: poll again after a short pause with
+            // the lock released (a timed wait would sleep for the timer
+            // slack, tens of microseconds, before noticing a finished batch)
+            lk.unlock();
+            const double t_pause = now_s() + 2e-6;
+            while (now_s() < t_pause) std::this_thread::yield();
+            lk.lock();
+        }
         else if (S->pending.empty() && !S->stopping)
             S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
     }
