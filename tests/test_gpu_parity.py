@@ -356,15 +356,16 @@ def test_unaligned_L_and_bytes_around_it(n_props):
     finally:
         lbl.free_abstraction(h)
 
-@pytest.mark.parametrize("n_props", [6, 12, 20, 34, 48, 60, 62, 64])
+@pytest.mark.parametrize("n_props", [2, 3, 4, 6, 12, 20, 34, 48, 60, 62, 64])
 @pytest.mark.parametrize("o_off", [0, 1, 2, 4])
 def test_frame_bytes_at_every_load_width(n_props, o_off):
     """O starting o_off bytes into a larger device buffer, for proposition
     counts whose rows the table kernels read in 16-byte units taken in
     memory order (64), in 16-, 4- or 2-byte pieces per cell (48, 60 and 12
     and 20, 6 and 34 and 62: more than one group of four loads for 20, 34, 60
-    and 62) or, once O is moved off those alignments, byte by byte: every
-    label equals the oracle's."""
+    and 62) or, once O is moved off those alignments, byte by byte; and
+    frames of 2, 3 and 4 propositions, whose per-word masks are read in 2-,
+    1- and 4-byte pieces: every label equals the oracle's."""
     rng = np.random.default_rng(500 + 7 * n_props + o_off)
     nx, ny = 48, 40
     a = random_csr(rng, 9000, nx, ny, 0.04)
