@@ -7,8 +7,8 @@
 // Whenever a slot is free and requests are pending, the worker forms a batch
 // from the front of the queue (at most max_batch_frames requests, as many as
 // fit the arena: admission by memory) and launches it with the same
-// persistent kernel as lbl_label_batch, while earlier batches are still
-// running on the other slots.  Requests that arrive meanwhile join the next
+// persistent kernel as lbl_label_batch (a batch of one frame: the one-frame
+// kernels), while earlier batches are still running on the other slots.  Requests that arrive meanwhile join the next
 // batch.  While batches are in flight the worker polls their completion
 // events every few microseconds (it sleeps on a condition variable only when
 // idle).  Latency is completion minus submission on the host's monotonic
@@ -25,6 +25,7 @@
 #include <unordered_map>
 
 #include "batch.h"
+#include "sparse.h"
 
 namespace {
 
@@ -125,6 +126,19 @@ void launch(lbl_server *S, Slot &sl, std::vector<Request> &take, BatchPlan &plan
     if (S->fault_batch > 0 && (int64_t)S->batches == S->fault_batch) {
         finish_slot(S, sl, LBL_EDEVICE, "injected batch failure");
         return;
+    }
+    // a batch of one frame on an abstraction with the sparse layout runs the
+    // one-frame kernels, with the slot's arena as their workspace: no batch
+    // tables to upload and one launch fewer (the labels are the same)
+    if (sl.reqs.size() == 1) {
+        const JobRef &j = sl.reqs.front().job;
+        if (j.a->sp != nullptr && swm_frame_workspace_bytes(j.a, j.n_props) <= sl.arena_bytes) {
+            lbl_status st = run_swm(j.a, j.O, j.n_props, sl.arena, j.L, sl.stream, false);
+            hipError_t e = st == LBL_OK ? hipEventRecord(sl.done, sl.stream) : hipSuccess;
+            if (st != LBL_OK) finish_slot(S, sl, st, "frame launch failed");
+            else if (e != hipSuccess) finish_slot(S, sl, LBL_EDEVICE, hipGetErrorString(e));
+            return;
+        }
     }
     BatchBuffers bufs;
     std::vector<uint8_t> img;
