@@ -112,13 +112,24 @@ void finish_slot(lbl_server *S, Slot &sl, lbl_status st, const std::string &msg)
 }
 
 // Launch the requests in `take` on slot `sl` (lock held).
-void launch(lbl_server *S, Slot &sl, std::vector<Request> &take, BatchPlan &plan)
+// Whether a batch of this one request runs the one-frame kernels on slot sl
+// (the abstraction has the sparse layout and their workspace fits the arena).
+bool runs_alone(const Slot &sl, const Request &r)
+{
+    return r.job.a->sp != nullptr && swm_frame_workspace_bytes(r.job.a, r.job.n_props) <= sl.arena_bytes;
+}
+
+// Launch the requests in take on slot sl: plan is their batch plan, or null
+// for a single request that runs alone.
+void launch(lbl_server *S, Slot &sl, std::vector<Request> &take, const BatchPlan *plan)
 {
     S->batches++;
     sl.reqs.swap(take);
-    sl.pairs = plan.pairs;
+    const JobRef &j0 = sl.reqs.front().job;
+    const bool alone = sl.reqs.size() == 1 && runs_alone(sl, sl.reqs.front());
+    sl.pairs = plan ? plan->pairs : j0.a->n_traj * j0.n_props;
     sl.busy = true;
-    sl.used = plan.device_bytes();
+    sl.used = plan ? plan->device_bytes() : swm_frame_workspace_bytes(j0.a, j0.n_props);
     S->in_flight += sl.reqs.size();
     S->max_in_flight = std::max<uint64_t>(S->max_in_flight, S->in_flight);
     S->budget_used += sl.used;
@@ -130,19 +141,20 @@ void launch(lbl_server *S, Slot &sl, std::vector<Request> &take, BatchPlan &plan
     // a batch of one frame on an abstraction with the sparse layout runs the
     // one-frame kernels, with the slot's arena as their workspace: no batch
     // tables to upload and one launch fewer (the labels are the same)
-    if (sl.reqs.size() == 1) {
-        const JobRef &j = sl.reqs.front().job;
-        if (j.a->sp != nullptr && swm_frame_workspace_bytes(j.a, j.n_props) <= sl.arena_bytes) {
-            lbl_status st = run_swm(j.a, j.O, j.n_props, sl.arena, j.L, sl.stream, false);
-            hipError_t e = st == LBL_OK ? hipEventRecord(sl.done, sl.stream) : hipSuccess;
-            if (st != LBL_OK) finish_slot(S, sl, st, "frame launch failed");
-            else if (e != hipSuccess) finish_slot(S, sl, LBL_EDEVICE, hipGetErrorString(e));
-            return;
-        }
+    if (alone) {
+        lbl_status st = run_swm(j0.a, j0.O, j0.n_props, sl.arena, j0.L, sl.stream, false);
+        hipError_t e = st == LBL_OK ? hipEventRecord(sl.done, sl.stream) : hipSuccess;
+        if (st != LBL_OK) finish_slot(S, sl, st, "frame launch failed");
+        else if (e != hipSuccess) finish_slot(S, sl, LBL_EDEVICE, hipGetErrorString(e));
+        return;
+    }
+    if (plan == nullptr) {
+        finish_slot(S, sl, LBL_EINVAL, "batch launched without a plan");
+        return;
     }
     BatchBuffers bufs;
     std::vector<uint8_t> img;
-    if (bind_batch(plan, sl.arena, sl.arena_bytes, &bufs, &img) != LBL_OK) {
+    if (bind_batch(*plan, sl.arena, sl.arena_bytes, &bufs, &img) != LBL_OK) {
         finish_slot(S, sl, LBL_ENOMEM, "batch does not fit the slot's arena");
         return;
     }
@@ -161,7 +173,7 @@ void launch(lbl_server *S, Slot &sl, std::vector<Request> &take, BatchPlan &plan
     }
     lbl_status st = LBL_OK;
     if (e == hipSuccess) {
-        st = enqueue_batch(plan, bufs, sl.stream);
+        st = enqueue_batch(*plan, bufs, sl.stream);
         if (st != LBL_OK) err = "batch launch failed";
     }
     if (e == hipSuccess && st == LBL_OK) e = hipEventRecord(sl.done, sl.stream);
@@ -205,6 +217,14 @@ void worker_main(lbl_server *S)
                 1e6 * (now_s() - S->pending.front().t_submit) < S->cfg.max_wait_us)
                 break;  // let the batch fill while the GPU is busy anyway
             std::vector<Request> take;
+            // a single pending request that runs alone needs no batch plan
+            if (S->pending.size() == 1 && runs_alone(sl, S->pending.front())) {
+                take.push_back(S->pending.front());
+                S->pending.pop_front();
+                launch(S, sl, take, nullptr);
+                any_busy = any_busy || sl.busy;
+                continue;
+            }
             BatchPlan plan;
             while (!S->pending.empty() && take.size() < S->cfg.max_batch_frames) {
                 take.push_back(S->pending.front());
@@ -230,7 +250,7 @@ void worker_main(lbl_server *S)
                 S->cv_done.notify_all();
                 continue;
             }
-            launch(S, sl, take, plan);
+            launch(S, sl, take, &plan);
             any_busy = any_busy || sl.busy;
         }
         if (S->stopping && S->pending.empty() && !any_busy) {
