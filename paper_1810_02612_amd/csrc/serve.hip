@@ -238,6 +238,14 @@ void worker_main(lbl_server *S)
                 plan = std::move(cand);
                 S->pending.pop_front();
             }
+            if (take.empty() && runs_alone(sl, S->pending.front())) {
+                // the head request fits no batch but runs alone
+                take.push_back(S->pending.front());
+                S->pending.pop_front();
+                launch(S, sl, take, nullptr);
+                any_busy = any_busy || sl.busy;
+                continue;
+            }
             if (take.empty()) {
                 // the head request cannot run (checked at submit, so only if it became invalid)
                 Request r = S->pending.front();
@@ -330,16 +338,23 @@ lbl_status lbl_serve_submit(lbl_server_t S, lbl_abs_t a, const uint8_t *O, uint3
     LBL_REQUIRE(a->device == S->device, "abstraction lives on another device than the server");
     Request r{0, JobRef{a, O, n_props, L}, now_s()};
     {
-        std::vector<Request> one{r};
-        BatchPlan plan;
-        bool ok = false;
-        const size_t need = batch_bytes(one, &plan, &ok);
+        // admission by memory: a request whose one-frame kernels fit a
+        // slot's arena can always run (alone, if no batch takes it); any
+        // other is admitted by the size of its batch plan
+        const bool alone = runs_alone(S->slots[0], r);
+        bool ok = true;
+        size_t need = 0;
+        if (!alone) {
+            std::vector<Request> one{r};
+            BatchPlan plan;
+            need = batch_bytes(one, &plan, &ok);
+        }
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stopping) {
             set_error("server is stopping");
             return LBL_ECLOSED;
         }
-        if (!ok || need > S->slots[0].arena_bytes) {
+        if (!alone && (!ok || need > S->slots[0].arena_bytes)) {
             S->rejected++;
             set_error("request needs " + std::to_string(need) + " bytes, more than a slot's share of the HBM budget");
             return LBL_ENOMEM;
