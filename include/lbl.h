@@ -354,7 +354,9 @@ lbl_status lbl_tune_describe(lbl_abs_t a, uint32_t n_props, char *buf, size_t bu
  * admitted onto the GPU as memory within hbm_budget_bytes (for the server's
  * internal per-request buffers) frees up, grouped per abstraction into
  * batches of at most max_batch_frames, and a batch is launched while earlier
- * ones are still running.  The library does not copy O or L: both must stay
+ * ones are still running (a batch of one frame on an abstraction with the
+ * sparse layout runs the kernels lbl_label_frame's sparse path runs; the
+ * labels are the same either way).  The library does not copy O or L: both must stay
  * valid until lbl_serve_wait returns LBL_OK for the ticket.  The server's
  * streams are not ordered after the caller's: O (and any earlier write to L)
  * must be complete on the device when lbl_serve_submit is called, e.g. by
