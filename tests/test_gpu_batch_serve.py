@@ -192,13 +192,13 @@ def serve_and_check(server, reqs, n_threads=3):
     assert not errors, errors[:5]
 
 
-def requests(abstractions, n, seed):
+def requests(abstractions, n, seed, props=(8, 65)):
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n):
         i = int(rng.integers(0, len(abstractions)))
         x = abstractions[i]
-        O = frames_for(x, i, 200 + seed * 1000 + k, n_props=int(rng.integers(8, 65)))
+        O = frames_for(x, i, 200 + seed * 1000 + k, n_props=int(rng.integers(*props)))
         out.append((x.h, torch.from_numpy(O).cuda(), O.shape[1],
                     torch.full((x.a.n_traj, O.shape[1]), 9, dtype=torch.uint8, device="cuda"), x.expect(O)))
     torch.cuda.synchronize()
@@ -215,6 +215,25 @@ def test_serve_matches_oracle_under_concurrency(abstractions):
         assert st["completed"] == 40 and st["failed"] == 0
         assert st["p50_ms"] > 0 and st["p99_ms"] >= st["p50_ms"]
         assert st["budget_high_water"] <= 256 << 20
+    finally:
+        lbl.serve_stop(s)
+
+
+def test_serve_few_propositions_match_oracle(abstractions):
+    # frames of one to four propositions: a request served alone runs the
+    # one-frame kernels for so few propositions (the direct-mask kernels
+    # where the layout has them) in its slot's arena, requests served
+    # together the batch kernels
+    reqs = requests(abstractions, 24, seed=7, props=(1, 5))
+    say("serve 24 requests of 1-4 propositions: 8 one at a time, 16 from 3 threads")
+    s = lbl.serve_start(hbm_budget_bytes=256 << 20, max_batch_frames=8, max_wait_us=0, n_streams=2)
+    try:
+        for (h, Od, n_props, Ld, want) in reqs[:8]:
+            assert lbl.serve_wait(s, lbl.serve_submit(s, h, Od, n_props, Ld)) == lbl.OK
+            assert np.array_equal(Ld.cpu().numpy(), want)
+        serve_and_check(s, reqs[8:])
+        st = lbl.serve_stats(s)
+        assert st["completed"] == 24 and st["failed"] == 0, st
     finally:
         lbl.serve_stop(s)
 
