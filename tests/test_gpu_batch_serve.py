@@ -238,6 +238,37 @@ def test_serve_few_propositions_match_oracle(abstractions):
         lbl.serve_stop(s)
 
 
+@pytest.mark.parametrize("n_props", [1, 8, 64])
+def test_serve_degenerate_abstractions(n_props):
+    """Served one at a time: an abstraction with no set cell (every label 0,
+    every byte of L still written over its 9s) and one trajectory with one
+    set cell (labels equal that cell's row of O)."""
+    rng = np.random.default_rng(40 + n_props)
+    nx = ny = 64
+    O = rng.integers(0, 2, (nx * ny, n_props)).astype(np.uint8)
+    O[1234] = 1
+    cases = [(np.zeros(301, np.uint64), np.zeros(0, np.uint32), 300),
+             (np.array([0, 1], np.uint64), np.array([1234], np.uint32), 1)]
+    hs = [lbl.load_abstraction(nx, ny, rp, ci) for rp, ci, _ in cases]
+    s = lbl.serve_start(hbm_budget_bytes=64 << 20, max_batch_frames=4, max_wait_us=0, n_streams=1)
+    try:
+        Od = torch.from_numpy(O).cuda()
+        for h, (rp, ci, n_traj) in zip(hs, cases):
+            want = oracle.label_csr(rp, ci, nx * ny, O)
+            assert want.sum() == (0 if ci.size == 0 else n_props)
+            for _ in range(2):
+                Ld = torch.full((n_traj, n_props), 9, dtype=torch.uint8, device="cuda")
+                torch.cuda.synchronize()
+                assert lbl.serve_wait(s, lbl.serve_submit(s, h, Od, n_props, Ld)) == lbl.OK
+                assert np.array_equal(Ld.cpu().numpy(), want)
+        st = lbl.serve_stats(s)
+        assert st["completed"] == 4 and st["failed"] == 0, st
+    finally:
+        lbl.serve_stop(s)
+        for h in hs:
+            lbl.free_abstraction(h)
+
+
 def test_serve_result_same_alone_and_in_the_mix(abstractions):
     x, i = abstractions[5], 5
     O = frames_for(x, i, 999, n_props=37)
